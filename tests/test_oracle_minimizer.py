@@ -1,0 +1,269 @@
+"""Pins of the oracle's minimiser: the midpoint step of eq. (7), the BB
+iteration of eqs. (8)-(12), the stop rule and the sweep.
+
+Independent facts used: geometry of the Cayley rotation, an in-plane
+angle-only re-derivation of the whole iteration for one cell, the
+Stoner-Wohlfarth switching astroid, a 1-D root find of the equilibrium angle
+and a general-purpose optimiser on a few cells.
+"""
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq, minimize as sp_minimize
+
+from oracle import fields, minimizer as mz
+
+MU0 = 4e-7 * np.pi
+
+
+def random_unit(shape, seed):
+    rng = np.random.default_rng(seed)
+    m = rng.standard_normal((3,) + shape)
+    return m / np.linalg.norm(m, axis=0)
+
+
+def small_problem(**kw):
+    args = dict(Ms=8e5, A=1.3e-11, Ku=500.0, u=(1, 0, 0), H_ext=(2e4, 5e3, -1e3))
+    args.update(kw)
+    return fields.Problem(6, 4, 2, 5e-9, 5e-9, 5e-9, **args)
+
+
+# ---------------------------------------------------------------- midpoint step
+def test_midpoint_step_preserves_norm_exactly():
+    P = small_problem()
+    m = random_unit((2, 4, 6), 1)
+    H = P.heff(m)
+    mp = mz.midpoint_step(m, H, 3e-5)           # large step on purpose
+    assert np.max(np.abs(np.linalg.norm(mp, axis=0) - 1.0)) < 1e-14
+
+
+def test_midpoint_step_is_a_rotation_about_m_cross_h():
+    """The Cayley map of b x . rotates m about b = (tau/2) m x H by the
+    angle 2 atan(|b| ...) -- here checked as: m+ - m is orthogonal to b, and
+    the angle between m and m+ is 2 atan(tau |m x H| / 2) (m is orthogonal
+    to b, so the full rotation angle shows)."""
+    P = small_problem()
+    m = random_unit((2, 4, 6), 2)
+    H = P.heff(m)
+    tau = 2e-5
+    mp = mz.midpoint_step(m, H, tau)
+    a = mz.cross(m, H)
+    ahat = a / np.linalg.norm(a, axis=0)
+    assert np.max(np.abs(np.sum((mp - m) * ahat, axis=0))) < 1e-14
+    ang = np.arctan2(np.linalg.norm(mz.cross(m, mp), axis=0), np.sum(m * mp, axis=0))
+    expect = 2 * np.arctan(tau * np.linalg.norm(a, axis=0) / 2)
+    assert np.max(np.abs(ang - expect)) < 1e-12
+    # the rotation moves m toward the tangential field (descent)
+    Hperp = H - np.sum(H * m, axis=0) * m
+    assert np.all(np.sum((mp - m) * Hperp, axis=0) > 0)
+
+
+def test_midpoint_step_first_order_is_projected_gradient():
+    """For small tau, (m+ - m)/tau -> -g = -m x (m x H) (eq. (6), descent)."""
+    P = small_problem()
+    m = random_unit((2, 4, 6), 3)
+    H = P.heff(m)
+    g = mz.projected_direction(m, H)
+    gmax = np.max(np.linalg.norm(g, axis=0))
+    errs = []
+    for tau in (1e-9, 1e-10):
+        d = (mz.midpoint_step(m, H, tau) - m) / tau
+        errs.append(np.max(np.abs(d + g)))
+        assert errs[-1] < tau * gmax * gmax          # second-order remainder
+    assert 8 < errs[0] / errs[1] < 12                # and it shrinks like tau
+
+
+def test_step_length_over_tau_formula():
+    """|m+ - m| / tau = |g| / sqrt(1 + (tau |g| / 2)^2) cell by cell."""
+    P = small_problem()
+    m = random_unit((2, 4, 6), 4)
+    H = P.heff(m)
+    tau = 5e-5
+    g = mz.projected_direction(m, H)
+    gn = np.linalg.norm(g, axis=0)
+    lhs = np.linalg.norm(mz.midpoint_step(m, H, tau) - m, axis=0) / tau
+    assert np.allclose(lhs, gn / np.sqrt(1 + (tau * gn / 2) ** 2), rtol=1e-12)
+
+
+def test_printed_plus_sign_climbs_and_descent_reading_falls():
+    """Reading R1: with the printed '+' the midpoint step raises U."""
+    P = small_problem()
+    m = random_unit((2, 4, 6), 5)
+    H = P.heff(m)
+    tau = 1e-7
+    E0 = P.energy(m)
+    down = P.energy(mz.normalise(mz.midpoint_step(m, H, tau)))
+    up = P.energy(mz.normalise(mz.midpoint_step(m, H, -tau)))   # the printed sign
+    assert down < E0 < up
+
+
+def test_fixed_small_tau_is_monotone():
+    P = small_problem()
+    m = random_unit((2, 4, 6), 6)
+    E = [P.energy(m)]
+    for _ in range(60):
+        m = mz.normalise(mz.midpoint_step(m, P.heff(m), mz.default_tau0(P.Ms)))
+        E.append(P.energy(m))
+    assert np.all(np.diff(E) < 0)
+
+
+# ---------------------------------------------------------------- BB iteration
+def sw_angle_iteration(theta0, HK, h, psiH, Ms, tau0, n_iter):
+    """Independent in-plane re-derivation for one cell with uniaxial
+    anisotropy along x and an in-plane field: the midpoint step is the
+    rotation theta -> theta + 2 atan(tau h_t / 2), with h_t the tangential
+    effective field; s and y are built from angles."""
+    def ht(t):
+        return -HK * np.sin(t) * np.cos(t) + h * np.sin(psiH - t)
+
+    def vec_m(t):
+        return np.array([np.cos(t), np.sin(t)])
+
+    def vec_g(t):
+        return -ht(t) * np.array([-np.sin(t), np.cos(t)])
+
+    th, tau = theta0, tau0
+    thetas = [th]
+    prev = None
+    for k in range(n_iter):
+        if k > 0:
+            s = vec_m(th) - vec_m(prev)
+            y = vec_g(th) - vec_g(prev)
+            ss, sy, yy = s @ s, s @ y, y @ y
+            cand = ss / abs(sy) if k % 2 == 1 else abs(sy) / yy
+            if np.isfinite(cand) and cand > 0:
+                tau = cand
+        prev = th
+        th = th + 2 * np.arctan(tau * ht(th) / 2)
+        thetas.append(th)
+    return np.array(thetas)
+
+
+def test_bb_iteration_matches_angle_rederivation():
+    """Whole trajectory, step by step, before the 1-D problem converges
+    (BB overshoots in steps 3 and 5 here, so the alternation and the
+    |s.y| guard are exercised)."""
+    Ms, K = 8e5, 500.0
+    HK = 2 * K / (MU0 * Ms)
+    h, psiH = 0.2 * HK, np.deg2rad(170.0)
+    th0 = 2.5
+    m0 = np.array([np.cos(th0), np.sin(th0), 0.0]).reshape(3, 1, 1, 1)
+    ref = sw_angle_iteration(th0, HK, h, psiH, Ms, mz.default_tau0(Ms), 7)
+    assert np.any(np.diff(ref) < 0) and np.any(np.diff(ref) > 0)
+    for n in range(1, 8):
+        # the self-demag of one cube is parallel to m (no torque); it is left
+        # out so that its rounding (~Ms eps) does not enter the tiny first s, y
+        P = fields.Problem(1, 1, 1, 5e-9, 5e-9, 5e-9, Ms=Ms, A=0.0, Ku=K, u=(1, 0, 0),
+                           H_ext=(h * np.cos(psiH), h * np.sin(psiH), 0.0),
+                           include_demag=False)
+        res = mz.minimize(P, m0, tol=0.0, max_iter=n, record=True)
+        th_n = np.arctan2(res["m"][1].item(), res["m"][0].item())
+        # the first step is ~1e-6 rad, so s and y carry a relative rounding of
+        # ~eps/1e-6; the 1-rad BB step that follows inherits ~1e-10 rad
+        assert abs(np.angle(np.exp(1j * (th_n - ref[n])))) < 2e-9, (n, th_n, ref[n])
+    assert res["taus"][0] == mz.default_tau0(Ms) and res["taus"][1] != res["taus"][0]
+
+
+def sw_switching_field(psi):
+    return 1.0 / (np.cos(psi) ** (2 / 3) + np.sin(psi) ** (2 / 3)) ** 1.5
+
+
+@pytest.mark.parametrize("psi_deg", [0.0, 45.0, 20.0])
+def test_stoner_wohlfarth_switching(psi_deg):
+    """One cubic cell (isotropic self-demag, no exchange): the metastable
+    state survives just below the astroid field and switches just above."""
+    Ms, K = 8e5, 500.0
+    HK = 2 * K / (MU0 * Ms)
+    psi = np.deg2rad(psi_deg)
+    hsw = sw_switching_field(psi)
+    m0 = np.array([np.cos(1e-3), np.sin(1e-3), 0.0]).reshape(3, 1, 1, 1)
+    for factor, survives in ((0.98, True), (1.02, False)):
+        h = factor * hsw * HK
+        P = fields.Problem(1, 1, 1, 5e-9, 5e-9, 5e-9, Ms=Ms, A=0.0, Ku=K, u=(1, 0, 0),
+                           H_ext=(-h * np.cos(psi), -h * np.sin(psi), 0.0))
+        r = mz.minimize(P, m0, tol=1e-10, max_iter=200000)
+        assert r["converged"]
+        assert (r["m"][0].item() > 0) == survives, (psi_deg, factor, r["m"].ravel())
+
+
+def test_stoner_wohlfarth_half_field_at_45():
+    assert abs(sw_switching_field(np.pi / 4) - 0.5) < 1e-15
+    assert sw_switching_field(0.0) == 1.0
+
+
+def test_equilibrium_angle_matches_root_find():
+    Ms, K = 8e5, 500.0
+    HK = 2 * K / (MU0 * Ms)
+    h, psiH = 0.3 * HK, np.deg2rad(30.0)
+    P = fields.Problem(1, 1, 1, 5e-9, 5e-9, 5e-9, Ms=Ms, A=0.0, Ku=K, u=(1, 0, 0),
+                       H_ext=(h * np.cos(psiH), h * np.sin(psiH), 0.0))
+    m0 = np.array([1.0, 0.0, 0.0]).reshape(3, 1, 1, 1)
+    r = mz.minimize(P, m0, tol=1e-12)
+    th = np.arctan2(r["m"][1].item(), r["m"][0].item())
+    root = brentq(lambda t: -HK * np.sin(t) * np.cos(t) + h * np.sin(psiH - t), 0.0, psiH,
+                  xtol=1e-15)
+    assert abs(th - root) < 1e-10
+    assert abs(r["m"][2].item()) < 1e-12
+
+
+def test_few_cells_against_general_optimiser():
+    """Four cells with demag, exchange, anisotropy and field: the BB result
+    is a stationary point and coincides with a quasi-Newton minimum over
+    spherical angles started from the same state."""
+    P = fields.Problem(2, 2, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=5e4,
+                       u=(0.0, 0.6, 0.8), H_ext=(3e4, -1e4, 2e4), demag="direct")
+    m0 = random_unit((1, 2, 2), 8)
+    r = mz.minimize(P, m0, tol=1e-11)
+    assert r["converged"]
+
+    th0 = np.arccos(np.clip(m0[2].ravel(), -1, 1))
+    ph0 = np.arctan2(m0[1].ravel(), m0[0].ravel())
+
+    def unpack(x):
+        th, ph = x[:4], x[4:]
+        return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph),
+                         np.cos(th)]).reshape(3, 1, 2, 2)
+
+    scale = 1.0 / abs(P.energy(m0))
+    sol = sp_minimize(lambda x: P.energy(unpack(x)) * scale, np.concatenate([th0, ph0]),
+                      method="BFGS", options={"gtol": 1e-13, "maxiter": 10000})
+    mb = unpack(sol.x)
+    assert np.max(np.abs(mb - r["m"])) < 1e-5
+    assert abs(P.energy(mb) - r["energy"]) < 1e-9 * abs(r["energy"])
+
+
+def test_bb_guard_rejects_degenerate_candidates():
+    assert mz.bb_candidate(1, 1.0, 0.0, 1.0) is None
+    assert mz.bb_candidate(2, 1.0, 1.0, 0.0) is None
+    assert mz.bb_candidate(2, 1.0, 0.0, 1.0) is None        # tau = 0 rejected
+    assert mz.bb_candidate(1, 2.0, -4.0, 1.0) == 0.5        # |s.y| used
+    assert mz.bb_candidate(2, 2.0, -4.0, 8.0) == 0.5
+
+
+def test_converged_start_takes_no_step_and_max_iter_caps():
+    P = fields.Problem(1, 1, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=0.0, Ku=500.0,
+                       H_ext=(1e4, 0.0, 0.0))
+    m0 = np.array([1.0, 0.0, 0.0]).reshape(3, 1, 1, 1)
+    r = mz.minimize(P, m0, tol=1e-6)
+    assert r["iters"] == 0 and r["heff_evals"] == 1 and r["converged"]
+    P2 = small_problem()
+    r2 = mz.minimize(P2, random_unit((2, 4, 6), 9), tol=0.0, max_iter=3)
+    assert r2["iters"] == 3 and not r2["converged"]
+
+
+def test_sweep_warm_start_repeated_field_costs_nothing():
+    P = small_problem()
+    H = np.array([[2e4, 0.0, 0.0], [2e4, 0.0, 0.0]])
+    out = mz.sweep(P, random_unit((2, 4, 6), 10), H, tol=1e-7)
+    assert out["converged"].all()
+    assert out["iters"][0] > 0 and out["iters"][1] == 0
+    assert np.allclose(out["mavg"][0], out["mavg"][1])
+
+
+def test_relaxation_lowers_energy_c0_like():
+    P = fields.Problem(16, 8, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=500.0)
+    m0 = random_unit((1, 8, 16), 12)
+    r = mz.minimize(P, m0, tol=1e-6, record=True)
+    assert r["converged"]
+    assert r["energy"] < P.energy(m0)
+    assert r["torques"][-1] < 1e-6
