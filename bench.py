@@ -1,0 +1,132 @@
+"""Throughput of the BB minimiser hot path on one MI355X.
+
+Workload: the 400 x 200 x 4 film of 5 nm cells (2000 x 1000 x 20 nm, the
+Standard Problem #1 stand-in), Ms = 8e5 A/m, A = 1.3e-11 J/m, Ku = 500 J/m^3
+along x, field +50 mT along x tilted 1 degree toward y, start +x with 1e-3
+noise (seeded).  One step = one minimiser iteration: the effective field
+(FFT demag convolution, exchange, anisotropy, Zeeman), g, the torque, the
+energy and BB reductions, the step size and the midpoint update.  The timed
+region runs K iterations through the library's run-to-tolerance loop with a
+zero tolerance, so the device-side stop flag and the host polling are
+exercised as in a hysteresis sweep.  Inputs are resident in HBM before the
+clock starts.
+
+Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=400)
+    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-iters", type=int, default=20)
+    return p.parse_args()
+
+
+def run_gpu(prec, steps, warmup, w, profile):
+    import torch
+    from paper_1405_2728_amd import Context
+    nx, ny, nz = w["n"]
+    ctx = Context(prec)
+    ctx.set_geometry(0, nx, ny, nz, *w["d"])
+    ctx.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
+    ctx.set_field(0, w["fields"][0])
+    m = torch.tensor(w["m0"], dtype=torch.float64, device="cuda")
+    ctx.minimize_to_tol(0, m, tol=0.0, max_iter=warmup)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    t0 = time.perf_counter()
+    r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read() if profile else None
+    if profile:
+        ctx.profile(False)
+    kb = ctx.kernel_bytes(0)
+    ctx.close()
+    return {"iters": r["iters"], "evals": r["heff_evals"], "seconds": dt, "prof": prof,
+            "bytes": kb, "torque": r["torque"]}
+
+
+def cpu_baseline(w, iters):
+    from oracle import fields as of, minimizer as om
+    P = of.Problem(*w["n"], *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"],
+                   H_ext=w["fields"][0])
+    P.heff(w["m0"])                      # tensor and its transform: set-up, not timed
+    t0 = time.perf_counter()
+    om.minimize(P, w["m0"], tol=0.0, max_iter=iters)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": "%d minimiser iterations of the same 400x200x4 workload "
+                      "(numpy FFT convolution, single thread); tensor set-up excluded" % iters}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    w = synth.workload(1)
+    main_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=False)
+    prof_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=True)
+    other = "mixed" if a.prec == "fp64" else "fp64"
+    other_run = run_gpu(other, a.steps, a.warmup, w, profile=False)
+
+    ips = main_run["iters"] / main_run["seconds"]
+    # dominant kernel of the profiled pass
+    prof = prof_run["prof"]
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, n = prof[dom]
+    avg_s = ms / 1e3 / max(n, 1)
+    achieved = prof_run["bytes"][dom] / avg_s / 1e9
+    per_iter_bytes = sum(prof_run["bytes"][k] for k in prof if k != "finish")
+    kernel_ms = {k: (v[0] / max(v[1], 1)) for k, v in prof.items()}
+    out = {
+        "metric": "minimiser iterations/s (= H_eff evals/s) at 400x200x4",
+        "value": ips,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * main_run["seconds"] / main_run["iters"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "film 400x200x4 cells of 5 nm, SP1 material, +50 mT at 1 deg, "
+                               "BB midpoint minimiser", "precision": a.prec,
+                   "padded_grid": [1024, 512, 4]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0,
+                     "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+                     "avg_kernel_us": avg_s * 1e6},
+        "iteration_model": {"bytes_per_iter": per_iter_bytes,
+                            "GBps_per_iter": per_iter_bytes * ips / 1e9,
+                            "kernel_avg_us": {k: 1e3 * v for k, v in kernel_ms.items()}},
+        other: {"value": other_run["iters"] / other_run["seconds"], "unit": "iters/s"},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * mm.h -- C ABI of the MI355X (gfx950) finite-difference micromagnetic
+ * energy minimiser.
+ *
+ * Method: Abert, Wautischer, Bruckner, Satz, Suess, "Efficient
+ * Energyminimization in Finite-Difference Micromagnetics: Speeding up
+ * Hysteresis Computations" (arXiv:1405.2728).
+ *
+ *   Sec. 2, eq. (5)  effective field H_eff = -(1/(mu0 Ms)) dU/dm
+ *   Sec. 2, eq. (7)  midpoint (Cayley) projected-gradient update, read with
+ *                    the descent sign:
+ *                    m_{k+1} = m_k - tau (m_k + m_{k+1})/2 x (m_k x H_eff(m_k))
+ *   Sec. 2, eqs. (8)-(10)  g_k = m_k x (m_k x H_eff(m_k)), s = m_k - m_{k-1},
+ *                    y = g_k - g_{k-1}
+ *   Sec. 2, eq. (12) Barzilai-Borwein steps tau1 = sum s.s / |sum s.y| (odd k)
+ *                    and tau2 = |sum s.y| / sum y.y (even k), used
+ *                    alternately; a candidate that is not finite and positive
+ *                    keeps the previous tau; first step tau0 = 1e-3/Ms
+ *   Sec. 2 (stop)    max_i |g_k^i| / Ms < tol, checked before every update
+ *   Sec. 3           demagnetisation field as a zero-padded FFT convolution on
+ *                    a regular cuboid grid
+ *   Sec. 4           hysteresis loop: one minimiser run per field, started
+ *                    from the previous field's magnetisation
+ *
+ * Field terms (the paper names them without formulas; standard FD forms):
+ *   demag      H_d,i  = -Ms sum_j N(r_i - r_j) m_j, N the cell-averaged
+ *              tensor (Newell closed form below 6 cell edges, Gauss-Legendre
+ *              quadrature of the same integral beyond)
+ *   exchange   H_ex,i = 2A/(mu0 Ms) sum_{6 face neighbours j} (m_j - m_i)/D^2,
+ *              missing neighbours omitted (free boundary)
+ *   anisotropy H_an,i = 2 Ku_i/(mu0 Ms) (m_i . u) u
+ *   Zeeman     H_ext
+ *   energy     U = -mu0 Ms V sum_i m_i . ((H_d + H_ex + H_an)_i/2 + H_ext)
+ *   mu0 = 4 pi 1e-7; SI units; fields in A/m; energies in J.
+ *
+ * Memory layout of every magnetisation / field argument: device memory,
+ * double precision, structure of arrays [3][nz][ny][nx] (x fastest), i.e.
+ * component c of cell (x, y, z) at index c*N + (z*ny + y)*nx + x with
+ * N = nx*ny*nz.  The caller owns these buffers; the library never frees or
+ * retains them beyond the call.  Host pointers are marked "host".
+ *
+ * Precision: MM_FP64 computes everything in double.  MM_MIXED computes the
+ * demag convolution (FFT passes and tensor product) in single precision and
+ * keeps double precision for the tensor set-up, the local field terms, the
+ * step-size and energy reductions, the stop test and the update; its
+ * arguments are double precision as well.
+ *
+ * Streams: all work is ordered on the stream given to mm_create (NULL =
+ * the default stream).  Calls that return host values synchronise that
+ * stream.  A context is not thread-safe.
+ *
+ * Errors: every function returns MM_OK (0), a non-fatal status (> 0) or an
+ * error (< 0).  mm_last_error() returns a message for the last error of a
+ * context.  On error no caller buffer has been written unless stated.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_ctx mm_ctx;
+
+enum mm_prec { MM_FP64 = 0, MM_MIXED = 1 };
+
+enum mm_status {
+  MM_OK = 0,
+  MM_NOT_CONVERGED = 1,   /* max_iter reached before the stop rule held   */
+  MM_STALLED = 2,         /* mixed form: torque stopped improving (floor)  */
+  MM_EINVAL = -1,         /* invalid argument                              */
+  MM_ENOMEM = -2,         /* device allocation failed                      */
+  MM_EHIP = -3,           /* HIP runtime error                             */
+  MM_ENONFINITE = -4,     /* non-finite torque or energy encountered       */
+  MM_ESTATE = -5,         /* call out of order (e.g. no geometry yet)      */
+  MM_EUNSUPPORTED = -6    /* grid shape not supported by this build        */
+};
+
+/* Per-iteration information (host struct). torque is max|g|/Ms before the
+ * update, energy U(m_k) in J, tau the step applied, k the iteration index. */
+typedef struct {
+  double tau;
+  double torque;
+  double energy;
+  int64_t k;
+} mm_step_info;
+
+/* Result of a minimiser run (host struct). iters = updates performed,
+ * heff_evals = effective-field evaluations (the paper's Tab. 1 unit). */
+typedef struct {
+  int status;
+  int64_t iters;
+  int64_t heff_evals;
+  double torque;
+  double energy;
+} mm_min_result;
+
+/* Create a context for n_samples independent problems (n_samples >= 1).
+ * prec is an mm_prec value; hip_stream is a hipStream_t or NULL.
+ * *out receives the context (owned by the caller; free with mm_destroy). */
+int mm_create(mm_ctx** out, int prec, int n_samples, void* hip_stream);
+
+/* Release every device resource of ctx. NULL is accepted. */
+void mm_destroy(mm_ctx* ctx);
+
+/* Define the regular cuboid grid of one sample (Sec. 3): nx, ny, nz >= 1
+ * cells of dx x dy x dz metres.  Computes the demag tensor spectrum on the
+ * device (once per geometry) and allocates the sample's work buffers.
+ * Resets the minimiser state.  MM_EUNSUPPORTED if the shape exceeds what
+ * this build's kernels handle (see mm_supported). */
+int mm_set_geometry(mm_ctx* ctx, int sample, int nx, int ny, int nz,
+                    double dx, double dy, double dz);
+
+/* Material of one sample (Sec. 4 notation): Ms > 0 (A/m), A >= 0 (J/m),
+ * uniaxial Ku (J/m^3) with easy axis u (host double[3], normalised here).
+ * Ku_map: NULL, or a device double[N] per-cell anisotropy constant that
+ * overrides Ku; the library copies it.  Requires mm_set_geometry first.
+ * Resets the minimiser state. */
+int mm_set_material(mm_ctx* ctx, int sample, double Ms, double A, double Ku,
+                    const double* u, const double* Ku_map);
+
+/* Uniform external field H (host double[3], A/m).  Resets the minimiser
+ * state (each field starts a new run, Sec. 4). */
+int mm_set_field(mm_ctx* ctx, int sample, const double* H);
+
+/* Reset the minimiser state: next iteration is k = 0 with tau = tau0. */
+int mm_reset(mm_ctx* ctx, int sample);
+
+/* Effective field of eq. (5) at m: H = H_d + H_ex + H_an + H_ext
+ * (device in m, device out H, both [3][N] double). */
+int mm_heff(mm_ctx* ctx, int sample, const double* m, double* H);
+
+/* Individual field terms at m; each output is a device [3][N] double or
+ * NULL to skip it. */
+int mm_field_terms(mm_ctx* ctx, int sample, const double* m, double* H_demag,
+                   double* H_exchange, double* H_anisotropy);
+
+/* Energy U(m) (host *E, J) and optionally its four terms (host double[4]:
+ * demag, exchange, anisotropy, Zeeman; may be NULL).  Synchronises. */
+int mm_energy(mm_ctx* ctx, int sample, const double* m, double* E, double* terms4);
+
+/* One iteration of the minimiser on m (device [3][N], updated in place):
+ * H_eff(m_k), g_k, the stop test, the step size of eq. (12) and the update
+ * of eq. (7).  Continues the current run (state kept in the context; call
+ * mm_reset before starting on a different m).  Returns MM_OK when the
+ * update was applied, MM_OK with info->torque < tol semantics left to the
+ * caller (this call applies no stop rule), MM_ENONFINITE on NaN/Inf.
+ * info (host, may be NULL) receives tau, torque and energy of m_k.
+ * Synchronises when info is not NULL. */
+int mm_minimize_step(mm_ctx* ctx, int sample, double* m, mm_step_info* info);
+
+/* Run the minimiser from m (device [3][N], updated in place) until
+ * max|g|/Ms < tol or max_iter updates.  Starts a fresh run (k = 0,
+ * tau = tau0).  out (host, may be NULL) receives the result.  Returns
+ * MM_OK (converged), MM_NOT_CONVERGED, MM_STALLED or an error.
+ * Synchronises. */
+int mm_minimize_to_tol(mm_ctx* ctx, int sample, double* m, double tol,
+                       int64_t max_iter, mm_min_result* out);
+
+/* Hysteresis sweep (Sec. 4) of every sample: m is a host array of
+ * n_samples device pointers ([3][N_s] double each, updated in place);
+ * H is host double[n_samples][n_fields][3] (A/m).  For each field the
+ * sample's field is set, the state reset and the minimiser run to tol from
+ * the previous field's result.  m_avg (host double[n_samples][n_fields][3])
+ * receives the mean magnetisation after each field; iters (host
+ * int64_t[n_samples][n_fields], may be NULL) the updates per field.
+ * Returns the worst status over all runs (an error aborts the sweep). */
+int mm_hysteresis_sweep(mm_ctx* ctx, double* const* m, const double* H, int n_fields,
+                        double tol, int64_t max_iter, double* m_avg, int64_t* iters);
+
+/* Mean magnetisation of m (device [3][N]) into host double[3]. */
+int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
+
+/* Options (numeric): "tau0" (m/A; 0 = 1e-3/Ms), "poll_every" (iterations
+ * between host checks of the stop flag, default 32), "stall_iters" (mixed
+ * form: iterations without a new torque minimum before MM_STALLED, default
+ * 500; 0 disables), "use_graph" (1 = replay iteration batches as a HIP
+ * graph).  Unknown keys give MM_EINVAL. */
+int mm_set_option(mm_ctx* ctx, const char* key, double value);
+
+/* Counters of one sample since its last mm_set_geometry: total
+ * effective-field evaluations and updates (host int64_t outputs). */
+int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
+
+/* Whether this build's kernels handle a grid (1) or not (0). */
+int mm_supported(int prec, int nx, int ny, int nz);
+
+/* Per-kernel timing with HIP events on the context's stream.
+ * mm_profile(ctx, 1) starts recording (and clears totals), 0 stops.
+ * mm_profile_read(ctx, id, &ms, &launches) reads the accumulated time of
+ * kernel id (synchronises).  mm_kernel_name(id) names it (NULL past the
+ * last id).  mm_kernel_bytes(ctx, sample, id, &bytes) gives that kernel's
+ * algorithmic bytes per launch (compulsory reads + writes of its pass). */
+int mm_profile(mm_ctx* ctx, int enable);
+int mm_profile_read(mm_ctx* ctx, int kernel_id, double* total_ms, int64_t* launches);
+const char* mm_kernel_name(int kernel_id);
+int mm_kernel_bytes(mm_ctx* ctx, int sample, int kernel_id, double* bytes);
+
+const char* mm_strerror(int code);
+const char* mm_last_error(const mm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

@@ -1,0 +1,758 @@
+// C ABI of the minimiser library: contexts, samples, the evaluation and
+// iteration sequences, polling, sweeps, timing.  See include/mm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+#include "mm_kernels.h"
+
+using namespace mmk;
+
+namespace {
+
+constexpr int kNumKernels = 6;
+const char* const kKernelNames[kNumKernels] = {"fwd_x", "yz_thin", "inv_x", "local", "finish",
+                                               "update"};
+enum { KID_FWD = 0, KID_YZ = 1, KID_INV = 2, KID_LOCAL = 3, KID_FINISH = 4, KID_UPDATE = 5 };
+
+struct Sample {
+  bool has_geom = false, has_mat = false;
+  int nx = 0, ny = 0, nz = 0, N = 0;
+  double dx = 0, dy = 0, dz = 0, V = 0;
+  int Px = 0, Py = 0, M = 0, Rx = 1;
+  double Ms = 0, A = 0, Ku = 0, u[3] = {1, 0, 0}, H[3] = {0, 0, 0};
+  double* ku_map = nullptr;
+  void* Tt = nullptr;
+  void* spec = nullptr;
+  void* twx = nullptr;
+  void* twy = nullptr;
+  double* Hd = nullptr;
+  double* g = nullptr;
+  double* s = nullptr;
+  double* partials = nullptr;
+  int nblk = 0;
+  MinState* st = nullptr;
+  MinState* st_eval = nullptr;
+  MinState* st_host = nullptr;
+  double* dev3 = nullptr;
+  double* host3 = nullptr;
+  int64_t evals_total = 0, iters_total = 0;
+};
+
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mm_ctx {
+  int prec = MM_FP64;
+  hipStream_t stream = nullptr;
+  std::vector<Sample> smp;
+  std::string err;
+  double tau0 = 0.0;
+  int poll_every = 32;
+  long long stall_iters = 500;
+  int use_graph = 0;
+  bool prof = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[kNumKernels] = {0};
+  int64_t prof_n[kNumKernels] = {0};
+};
+
+namespace {
+
+bool single(const mm_ctx* c) { return c->prec == MM_MIXED; }
+
+int fail(mm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((ctx), MM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int next_pow2(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_sample(Sample& s) {
+  dfree(s.ku_map);
+  dfree(s.Tt);
+  dfree(s.spec);
+  dfree(s.twx);
+  dfree(s.twy);
+  dfree(s.Hd);
+  dfree(s.g);
+  dfree(s.s);
+  dfree(s.partials);
+  dfree(s.st);
+  dfree(s.st_eval);
+  dfree(s.dev3);
+  if (s.st_host) (void)hipHostFree(s.st_host);
+  if (s.host3) (void)hipHostFree(s.host3);
+  s.st_host = nullptr;
+  s.host3 = nullptr;
+  s.has_geom = false;
+  s.has_mat = false;
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, double* x, double* w) {
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+int check_sample(mm_ctx* c, int sample, bool need_mat) {
+  if (!c) return MM_EINVAL;
+  if (sample < 0 || sample >= (int)c->smp.size())
+    return fail(c, MM_EINVAL, "sample index out of range");
+  const Sample& s = c->smp[sample];
+  if (!s.has_geom) return fail(c, MM_ESTATE, "mm_set_geometry has not been called");
+  if (need_mat && !s.has_mat) return fail(c, MM_ESTATE, "mm_set_material has not been called");
+  return MM_OK;
+}
+
+// ---- timing ------------------------------------------------------------------
+hipEvent_t take_event(mm_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct Timer {
+  mm_ctx* c;
+  int id;
+  hipEvent_t a = nullptr;
+  Timer(mm_ctx* ctx, int kid) : c(ctx), id(kid) {
+    if (c->prof) {
+      a = take_event(c);
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timer() {
+    if (c->prof) {
+      hipEvent_t b = take_event(c);
+      (void)hipEventRecord(b, c->stream);
+      c->prof_pending.push_back({id, a, b});
+    }
+  }
+};
+
+void prof_collect(mm_ctx* c) {
+  if (c->prof_pending.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_ms[r.id] += ms;
+      c->prof_n[r.id] += 1;
+    }
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+}
+
+// ---- tensor set-up ---------------------------------------------------------
+int build_tensor(mm_ctx* c, Sample& s) {
+  hipStream_t st = c->stream;
+  GaussRules gr;
+  gauss_legendre(6, gr.x6, gr.w6);
+  gauss_legendre(4, gr.x4, gr.w4);
+  gauss_legendre(3, gr.x3, gr.w3);
+  double* oct = nullptr;
+  double* E = nullptr;
+  void* EX = nullptr;
+  void* twx64 = nullptr;
+  void* twy64 = nullptr;
+  const size_t n_oct = 6ull * s.N;
+  const size_t n_E = 6ull * s.nz * s.Py * s.Px;
+  const size_t n_EX = (size_t)(s.M + 1) * 6 * s.nz * s.Py;
+  auto cleanup = [&]() {
+    dfree(oct);
+    dfree(E);
+    dfree(EX);
+    dfree(twx64);
+    dfree(twy64);
+  };
+  if (hipMalloc((void**)&oct, n_oct * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&E, n_E * sizeof(double)) != hipSuccess ||
+      hipMalloc(&EX, n_EX * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&twx64, (size_t)s.Px * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&twy64, (size_t)s.Py * 2 * sizeof(double)) != hipSuccess) {
+    cleanup();
+    return fail(c, MM_ENOMEM, "device allocation for the tensor set-up failed");
+  }
+  launch_twiddles(st, twx64, s.Px, false);
+  launch_twiddles(st, twy64, s.Py, false);
+  launch_newell_octant(st, oct, s.nx, s.ny, s.nz, s.dx, s.dy, s.dz, gr);
+  launch_embed_thin(st, oct, E, s.nx, s.ny, s.nz, s.Px, s.Py);
+  const int M = s.M;
+  int R = 8192 / M;
+  if (R > 8) R = 8;
+  if (R < 1) R = 1;
+  launch_fwd_x<double>(st, E, s.Px, s.Px, s.nz * s.Py, 6, s.Px, R, EX, twx64, nullptr);
+  launch_fft_cols<double>(st, EX, s.Py, (M + 1) * 6 * s.nz, twy64);
+  if (single(c)) launch_extract_thin<float>(st, EX, (float*)s.Tt, M, s.nz, s.Py);
+  else launch_extract_thin<double>(st, EX, (double*)s.Tt, M, s.nz, s.Py);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return fail(c, MM_EHIP, std::string("tensor set-up: ") + hipGetErrorString(e));
+  return MM_OK;
+}
+
+// ---- one effective-field evaluation ----------------------------------------
+struct EvalOut {
+  double* Hd = nullptr;       // demag output (NULL: internal buffer)
+  double* H = nullptr;        // total field
+  double* Hex = nullptr;
+  double* Han = nullptr;
+  bool iterate = false;       // minimiser iteration: g, BB sums, state
+  MinState* st = nullptr;     // state for finish (NULL: no finish)
+};
+
+void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
+  hipStream_t st = c->stream;
+  const int* done = o.iterate ? &o.st->done : nullptr;
+  const int rows = s.nz * s.ny;
+  double* Hd = o.Hd ? o.Hd : s.Hd;
+  {
+    Timer t(c, KID_FWD);
+    if (single(c))
+      launch_fwd_x<float>(st, m, s.nx, s.nx, rows, 3, s.Px, s.Rx, s.spec, s.twx, done);
+    else
+      launch_fwd_x<double>(st, m, s.nx, s.nx, rows, 3, s.Px, s.Rx, s.spec, s.twx, done);
+  }
+  {
+    Timer t(c, KID_YZ);
+    const double scale = -s.Ms / ((double)s.M * (double)s.Py);
+    if (single(c))
+      launch_yz_thin<float>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const float*)s.Tt, (float)scale,
+                            s.twy, done);
+    else
+      launch_yz_thin<double>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const double*)s.Tt, scale, s.twy,
+                             done);
+  }
+  {
+    Timer t(c, KID_INV);
+    if (single(c))
+      launch_inv_x<float>(st, s.spec, rows, 3, s.nx, s.Px, s.Rx, Hd, s.twx, done);
+    else
+      launch_inv_x<double>(st, s.spec, rows, 3, s.nx, s.Px, s.Rx, Hd, s.twx, done);
+  }
+  LocalArgs a;
+  a.m = m;
+  a.Hd = Hd;
+  a.g = o.iterate ? s.g : nullptr;
+  a.s = o.iterate ? s.s : nullptr;
+  a.Hout = o.H;
+  a.Hex_out = o.Hex;
+  a.Han_out = o.Han;
+  a.ku_map = s.ku_map;
+  a.nx = s.nx;
+  a.ny = s.ny;
+  a.nz = s.nz;
+  const double pre = 2.0 * s.A / (kMu0Host * s.Ms);
+  a.cx = pre / (s.dx * s.dx);
+  a.cy = pre / (s.dy * s.dy);
+  a.cz = pre / (s.dz * s.dz);
+  a.ku = s.Ku;
+  a.kan = 2.0 / (kMu0Host * s.Ms);
+  for (int q = 0; q < 3; ++q) {
+    a.u[q] = s.u[q];
+    a.H[q] = s.H[q];
+  }
+  a.partials = s.partials;
+  a.st = o.iterate ? o.st : nullptr;
+  a.done = done;
+  {
+    Timer t(c, KID_LOCAL);
+    launch_local(st, a);
+  }
+  if (o.st) {
+    Timer t(c, KID_FINISH);
+    launch_finish(st, s.partials, s.nblk, o.st, s.Ms, s.V);
+  }
+}
+
+void enqueue_iteration(mm_ctx* c, Sample& s, double* m) {
+  EvalOut o;
+  o.iterate = true;
+  o.st = s.st;
+  enqueue_eval(c, s, m, o);
+  Timer t(c, KID_UPDATE);
+  launch_update(c->stream, m, s.g, s.s, s.N, s.st);
+}
+
+double tau0_of(const mm_ctx* c, const Sample& s) { return c->tau0 > 0 ? c->tau0 : 1e-3 / s.Ms; }
+
+int status_of(int done) {
+  switch (done) {
+    case 1: return MM_OK;
+    case 2: return MM_NOT_CONVERGED;
+    case 3: return MM_STALLED;
+    case -1: return MM_ENONFINITE;
+    default: return MM_NOT_CONVERGED;
+  }
+}
+
+int read_state(mm_ctx* c, Sample& s) {
+  HIPCHK(c, hipMemcpyAsync(s.st_host, s.st, sizeof(MinState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
+                     single(c) ? c->stall_iters : 0, 0);
+  for (;;) {
+    for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, s, m);
+    HIPCHK(c, hipGetLastError());
+    int rc = read_state(c, s);
+    if (rc != MM_OK) return rc;
+    prof_collect(c);
+    if (s.st_host->done != 0) break;
+  }
+  const MinState& h = *s.st_host;
+  s.evals_total += h.evals;
+  s.iters_total += h.k;
+  if (out) {
+    out->status = status_of(h.done);
+    out->iters = h.k;
+    out->heff_evals = h.evals;
+    out->torque = h.torque;
+    out->energy = h.energy;
+  }
+  if (h.done == -1) return fail(c, MM_ENONFINITE, "non-finite torque or energy");
+  return status_of(h.done);
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+int mm_create(mm_ctx** out, int prec, int n_samples, void* hip_stream) {
+  if (!out) return MM_EINVAL;
+  *out = nullptr;
+  if ((prec != MM_FP64 && prec != MM_MIXED) || n_samples < 1) return MM_EINVAL;
+  mm_ctx* c = new mm_ctx();
+  c->prec = prec;
+  c->stream = (hipStream_t)hip_stream;
+  c->smp.resize(n_samples);
+  *out = c;
+  return MM_OK;
+}
+
+void mm_destroy(mm_ctx* c) {
+  if (!c) return;
+  bool any = false;
+  for (auto& s : c->smp) any = any || s.has_geom;
+  if (any || !c->prof_pending.empty() || !c->ev_pool.empty()) (void)hipStreamSynchronize(c->stream);
+  for (auto& s : c->smp) free_sample(s);
+  for (auto& r : c->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int mm_supported(int prec, int nx, int ny, int nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return 0;
+  if (nx > (1 << 14) || ny > (1 << 13)) return 0;
+  const int Px = next_pow2(2 * nx - 1) < 2 ? 2 : next_pow2(2 * nx - 1);
+  const int Py = next_pow2(2 * ny - 1);
+  if (Px / 2 > 8192) return 0;
+  return yz_thin_fits(nz, Py, prec == MM_MIXED) ? 1 : 0;
+}
+
+int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, double dy, double dz) {
+  if (!c) return MM_EINVAL;
+  if (sample < 0 || sample >= (int)c->smp.size()) return fail(c, MM_EINVAL, "sample index out of range");
+  if (nx < 1 || ny < 1 || nz < 1 || !(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) ||
+      !std::isfinite(dy) || !std::isfinite(dz))
+    return fail(c, MM_EINVAL, "grid sizes must be >= 1 and cell sizes positive");
+  if ((long long)nx * ny * nz > (1LL << 30)) return fail(c, MM_EINVAL, "grid too large");
+  if (!mm_supported(c->prec, nx, ny, nz))
+    return fail(c, MM_EUNSUPPORTED, "grid shape not supported by the thin-film kernels");
+  (void)hipStreamSynchronize(c->stream);
+  Sample& s = c->smp[sample];
+  const double Ms = s.Ms, A = s.A, Ku = s.Ku;
+  const double u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
+  const double H0 = s.H[0], H1 = s.H[1], H2 = s.H[2];
+  free_sample(s);
+  s.Ms = Ms; s.A = A; s.Ku = Ku;
+  s.u[0] = u0; s.u[1] = u1; s.u[2] = u2;
+  s.H[0] = H0; s.H[1] = H1; s.H[2] = H2;
+  s.nx = nx; s.ny = ny; s.nz = nz;
+  s.N = nx * ny * nz;
+  s.dx = dx; s.dy = dy; s.dz = dz;
+  s.V = dx * dy * dz;
+  s.Px = next_pow2(2 * nx - 1);
+  if (s.Px < 2) s.Px = 2;
+  s.Py = next_pow2(2 * ny - 1);
+  s.M = s.Px / 2;
+  const bool sp = single(c);
+  const int Rt = sp ? 16 : 8;
+  int R = 8192 / s.M;
+  if (R > Rt) R = Rt;
+  if (R < 1) R = 1;
+  if (R > nz * ny) R = nz * ny;
+  s.Rx = R;
+  const size_t creal = sp ? sizeof(float) : sizeof(double);
+  const size_t nT = (size_t)(s.M + 1) * nz * (s.Py / 2 + 1) * 6;
+  const size_t nspec = (size_t)(s.M + 1) * 3 * nz * ny;
+  s.nblk = local_blocks(s.N);
+  const size_t npart = (size_t)(s.nblk > 1 ? s.nblk : 1) * kNPartial;
+  bool ok = hipMalloc(&s.Tt, nT * creal) == hipSuccess &&
+            hipMalloc(&s.spec, nspec * 2 * creal) == hipSuccess &&
+            hipMalloc(&s.twx, (size_t)s.Px * 2 * creal) == hipSuccess &&
+            hipMalloc(&s.twy, (size_t)s.Py * 2 * creal) == hipSuccess &&
+            hipMalloc((void**)&s.Hd, 3ull * s.N * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&s.g, 3ull * s.N * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&s.s, 3ull * s.N * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&s.partials, npart * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&s.st, sizeof(MinState)) == hipSuccess &&
+            hipMalloc((void**)&s.st_eval, sizeof(MinState)) == hipSuccess &&
+            hipMalloc((void**)&s.dev3, 3 * sizeof(double)) == hipSuccess &&
+            hipHostMalloc((void**)&s.st_host, sizeof(MinState), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&s.host3, 3 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    free_sample(s);
+    (void)hipGetLastError();
+    return fail(c, MM_ENOMEM, "device allocation failed");
+  }
+  HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * sizeof(double), c->stream));
+  launch_twiddles(c->stream, s.twx, s.Px, sp);
+  launch_twiddles(c->stream, s.twy, s.Py, sp);
+  int rc = build_tensor(c, s);
+  if (rc != MM_OK) {
+    free_sample(s);
+    return rc;
+  }
+  s.has_geom = true;
+  s.has_mat = s.Ms > 0;
+  s.evals_total = s.iters_total = 0;
+  if (s.has_mat)
+    launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_set_material(mm_ctx* c, int sample, double Ms, double A, double Ku, const double* u,
+                    const double* Ku_map) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!(Ms > 0) || !std::isfinite(Ms) || !(A >= 0) || !std::isfinite(A) || !std::isfinite(Ku))
+    return fail(c, MM_EINVAL, "Ms must be > 0, A >= 0, Ku finite");
+  Sample& s = c->smp[sample];
+  double uu[3] = {1, 0, 0};
+  if (u) {
+    const double n = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(n > 0) || !std::isfinite(n)) return fail(c, MM_EINVAL, "easy axis must be non-zero");
+    for (int q = 0; q < 3; ++q) uu[q] = u[q] / n;
+  }
+  s.Ms = Ms;
+  s.A = A;
+  s.Ku = Ku;
+  for (int q = 0; q < 3; ++q) s.u[q] = uu[q];
+  if (Ku_map) {
+    if (!s.ku_map && hipMalloc((void**)&s.ku_map, (size_t)s.N * sizeof(double)) != hipSuccess) {
+      s.ku_map = nullptr;
+      return fail(c, MM_ENOMEM, "device allocation failed");
+    }
+    HIPCHK(c, hipMemcpyAsync(s.ku_map, Ku_map, (size_t)s.N * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    dfree(s.ku_map);
+  }
+  s.has_mat = true;
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_set_field(mm_ctx* c, int sample, const double* H) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!H || !std::isfinite(H[0]) || !std::isfinite(H[1]) || !std::isfinite(H[2]))
+    return fail(c, MM_EINVAL, "field must be three finite numbers");
+  Sample& s = c->smp[sample];
+  for (int q = 0; q < 3; ++q) s.H[q] = H[q];
+  if (s.has_mat) launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_reset(mm_ctx* c, int sample) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  Sample& s = c->smp[sample];
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_heff(mm_ctx* c, int sample, const double* m, double* H) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !H) return fail(c, MM_EINVAL, "null buffer");
+  EvalOut o;
+  o.H = H;
+  enqueue_eval(c, c->smp[sample], m, o);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_field_terms(mm_ctx* c, int sample, const double* m, double* H_demag, double* H_exchange,
+                   double* H_anisotropy) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m) return fail(c, MM_EINVAL, "null buffer");
+  EvalOut o;
+  o.Hd = H_demag;
+  o.Hex = H_exchange;
+  o.Han = H_anisotropy;
+  enqueue_eval(c, c->smp[sample], m, o);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_energy(mm_ctx* c, int sample, const double* m, double* E, double* terms4) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !E) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  launch_reset_state(c->stream, s.st_eval, 0.0, 0.0, 0, 0, 2);
+  EvalOut o;
+  o.st = s.st_eval;
+  enqueue_eval(c, s, m, o);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(s.st_host, s.st_eval, sizeof(MinState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  *E = s.st_host->energy;
+  if (terms4)
+    for (int q = 0; q < 4; ++q) terms4[q] = s.st_host->eterm[q];
+  if (!std::isfinite(*E)) return fail(c, MM_ENONFINITE, "non-finite energy");
+  return MM_OK;
+}
+
+int mm_minimize_step(mm_ctx* c, int sample, double* m, mm_step_info* info) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  launch_set_mode(c->stream, s.st, 1);
+  enqueue_iteration(c, s, m);
+  HIPCHK(c, hipGetLastError());
+  s.evals_total += 1;
+  s.iters_total += 1;
+  if (info) {
+    rc = read_state(c, s);
+    if (rc != MM_OK) return rc;
+    prof_collect(c);
+    info->tau = s.st_host->last_tau;
+    info->torque = s.st_host->torque;
+    info->energy = s.st_host->energy;
+    info->k = s.st_host->last_k;
+    if (s.st_host->done == -1) return fail(c, MM_ENONFINITE, "non-finite torque or energy");
+  }
+  return MM_OK;
+}
+
+int mm_minimize_to_tol(mm_ctx* c, int sample, double* m, double tol, int64_t max_iter,
+                       mm_min_result* out) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !(tol >= 0) || max_iter < 0) return fail(c, MM_EINVAL, "bad argument");
+  return run_to_tol(c, c->smp[sample], m, tol, max_iter, out);
+}
+
+int mm_mean(mm_ctx* c, int sample, const double* m, double* mavg) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!m || !mavg) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  launch_mean(c->stream, m, s.N, s.partials, s.dev3);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(s.host3, s.dev3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int q = 0; q < 3; ++q) mavg[q] = s.host3[q];
+  return MM_OK;
+}
+
+int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fields, double tol,
+                        int64_t max_iter, double* m_avg, int64_t* iters) {
+  if (!c) return MM_EINVAL;
+  if (!m || !H || !m_avg || n_fields < 0 || !(tol >= 0) || max_iter < 0)
+    return fail(c, MM_EINVAL, "bad argument");
+  const int S = (int)c->smp.size();
+  for (int k = 0; k < S; ++k) {
+    int rc = check_sample(c, k, true);
+    if (rc != MM_OK) return rc;
+    if (!m[k]) return fail(c, MM_EINVAL, "null magnetisation pointer");
+  }
+  int worst = MM_OK;
+  for (int k = 0; k < S; ++k) {
+    for (int f = 0; f < n_fields; ++f) {
+      const double* h = H + ((size_t)k * n_fields + f) * 3;
+      int rc = mm_set_field(c, k, h);
+      if (rc != MM_OK) return rc;
+      mm_min_result r;
+      rc = run_to_tol(c, c->smp[k], m[k], tol, max_iter, &r);
+      if (rc < 0) return rc;
+      if (rc > worst) worst = rc;
+      if (iters) iters[(size_t)k * n_fields + f] = r.iters;
+      rc = mm_mean(c, k, m[k], m_avg + ((size_t)k * n_fields + f) * 3);
+      if (rc != MM_OK) return rc;
+    }
+  }
+  return worst;
+}
+
+int mm_set_option(mm_ctx* c, const char* key, double value) {
+  if (!c || !key) return MM_EINVAL;
+  if (!std::isfinite(value)) return fail(c, MM_EINVAL, "option value must be finite");
+  if (!std::strcmp(key, "tau0")) {
+    if (value < 0) return fail(c, MM_EINVAL, "tau0 must be >= 0");
+    c->tau0 = value;
+  } else if (!std::strcmp(key, "poll_every")) {
+    if (value < 1 || value > 100000) return fail(c, MM_EINVAL, "poll_every out of range");
+    c->poll_every = (int)value;
+  } else if (!std::strcmp(key, "stall_iters")) {
+    if (value < 0) return fail(c, MM_EINVAL, "stall_iters must be >= 0");
+    c->stall_iters = (long long)value;
+  } else if (!std::strcmp(key, "use_graph")) {
+    c->use_graph = value != 0.0;
+  } else {
+    return fail(c, MM_EINVAL, std::string("unknown option ") + key);
+  }
+  return MM_OK;
+}
+
+int mm_counters(mm_ctx* c, int sample, int64_t* heff_evals, int64_t* iters) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (heff_evals) *heff_evals = c->smp[sample].evals_total;
+  if (iters) *iters = c->smp[sample].iters_total;
+  return MM_OK;
+}
+
+int mm_profile(mm_ctx* c, int enable) {
+  if (!c) return MM_EINVAL;
+  prof_collect(c);
+  c->prof = enable != 0;
+  if (c->prof)
+    for (int k = 0; k < kNumKernels; ++k) {
+      c->prof_ms[k] = 0;
+      c->prof_n[k] = 0;
+    }
+  return MM_OK;
+}
+
+int mm_profile_read(mm_ctx* c, int id, double* total_ms, int64_t* launches) {
+  if (!c || id < 0 || id >= kNumKernels) return MM_EINVAL;
+  prof_collect(c);
+  if (total_ms) *total_ms = c->prof_ms[id];
+  if (launches) *launches = c->prof_n[id];
+  return MM_OK;
+}
+
+const char* mm_kernel_name(int id) {
+  if (id < 0 || id >= kNumKernels) return nullptr;
+  return kKernelNames[id];
+}
+
+int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!bytes || id < 0 || id >= kNumKernels) return fail(c, MM_EINVAL, "bad argument");
+  const Sample& s = c->smp[sample];
+  const double sr = single(c) ? 4.0 : 8.0;
+  const double N3 = 3.0 * s.N * 8.0;                                  // one [3][N] double array
+  const double spec = (double)(s.M + 1) * 3 * s.nz * s.ny * 2 * sr;   // spectrum A
+  const double tens = (double)(s.M + 1) * s.nz * (s.Py / 2 + 1) * 6 * sr;
+  double b = 0;
+  switch (id) {
+    case KID_FWD: b = N3 + spec; break;
+    case KID_YZ: b = 2 * spec + tens; break;
+    case KID_INV: b = spec + N3; break;
+    case KID_LOCAL: b = 5 * N3 + (s.ku_map ? s.N * 8.0 : 0.0); break;  // m, Hd, g, s in; g out
+    case KID_FINISH: b = (double)s.nblk * kNPartial * 8.0; break;
+    case KID_UPDATE: b = 4 * N3; break;                                 // m, g in; m, s out
+  }
+  *bytes = b;
+  return MM_OK;
+}
+
+const char* mm_strerror(int code) {
+  switch (code) {
+    case MM_OK: return "ok";
+    case MM_NOT_CONVERGED: return "not converged within max_iter";
+    case MM_STALLED: return "torque stopped decreasing (precision floor)";
+    case MM_EINVAL: return "invalid argument";
+    case MM_ENOMEM: return "device allocation failed";
+    case MM_EHIP: return "HIP runtime error";
+    case MM_ENONFINITE: return "non-finite value";
+    case MM_ESTATE: return "call out of order";
+    case MM_EUNSUPPORTED: return "grid shape not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* mm_last_error(const mm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Device-side building blocks shared by the HIP kernels of the minimiser:
+// complex arithmetic, radix-2/4/8 butterflies, an in-place LDS Stockham FFT
+// stage, and deterministic block reductions.  gfx950 only (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmk {
+
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scl(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.x, -a.y); }
+// multiply by -i (DIR = -1) or +i (DIR = +1)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+  return DIR < 0 ? mk(a.y, -a.x) : mk(-a.y, a.x);
+}
+
+// ---------------------------------------------------------------------------
+// DFT of length R on registers, X[k] = sum_n v[n] exp(DIR 2 pi i n k / R).
+// ---------------------------------------------------------------------------
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = add(a, b);
+  v[1] = sub(a, b);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> a0 = add(v[0], v[2]), a1 = sub(v[0], v[2]);
+  cx<T> a2 = add(v[1], v[3]), a3 = rot90<DIR>(sub(v[1], v[3]));
+  v[0] = add(a0, a2);
+  v[2] = sub(a0, a2);
+  v[1] = add(a1, a3);
+  v[3] = sub(a1, a3);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<DIR>(e);
+  dft4<DIR>(o);
+  const T h = T(0.70710678118654752440084436210485);
+  // o[k] *= exp(DIR i pi k / 4)
+  o[1] = mk(h * (o[1].x - DIR * o[1].y), h * (o[1].y + DIR * o[1].x));
+  o[2] = rot90<DIR>(o[2]);
+  o[3] = mk(h * (-o[3].x - DIR * o[3].y), h * (-o[3].y + DIR * o[3].x));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = add(e[k], o[k]);
+    v[k + 4] = sub(e[k], o[k]);
+  }
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else dft8<DIR>(v);
+}
+
+// Twiddle exp(DIR 2 pi i m / twn) from a table tw[m] = exp(-2 pi i m / twn).
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int m) {
+  cx<T> w = tw[m];
+  return DIR < 0 ? w : conj(w);
+}
+
+// Radix plan of a power-of-two length n: 8s, with one 4 (p % 3 == 2) or two
+// 4s (p % 3 == 1); n = 2 uses a single radix-2 stage.  Encoded as the
+// number of leading radix-4 stages and radix-8 stages.
+struct FftPlan {
+  int n, n4, n8, n2;
+};
+
+__host__ __device__ inline FftPlan make_plan(int n) {
+  FftPlan p{n, 0, 0, 0};
+  int lg = 0;
+  while ((1 << lg) < n) ++lg;
+  if (lg == 0) return p;
+  if (lg == 1) { p.n2 = 1; return p; }
+  if (lg == 2) { p.n4 = 1; return p; }
+  int a = lg / 3, b = lg % 3;
+  if (b == 0) { p.n8 = a; }
+  else if (b == 1) { p.n4 = 2; p.n8 = a - 1; }
+  else { p.n4 = 1; p.n8 = a; }
+  return p;
+}
+
+// One in-place Stockham stage of radix R over nseq sequences of length n
+// stored at buf + s*stride.  Every thread first loads, twiddles and
+// transforms up to VPT/R butterflies into registers, then (after a barrier)
+// stores them: the in-place form needs all loads of a stage to precede its
+// stores, so the caller guarantees nseq*n <= VPT*nthr.
+//   butterfly j of a sequence (0 <= j < n/R), k = j mod Ns:
+//     v[r] = x[j + r n/R] * w^(r k),  w = exp(DIR 2 pi i / (Ns R))
+//     v    = DFT_R(v)
+//     y[(j div Ns) Ns R + k + r Ns] = v[r]
+template <int R, int DIR, int VPT, typename T>
+__device__ __forceinline__ void stockham_stage(cx<T>* buf, int n, int Ns, int nseq, int stride,
+                                               const cx<T>* __restrict__ tw, int twn, int tid,
+                                               int nthr) {
+  constexpr int BPT = VPT / R;
+  const int nbs = n / R;
+  const int nb = nbs * nseq;
+  const int twstep = twn / (Ns * R);
+  cx<T> v[BPT][R];
+  int dst[BPT];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int t = tid + q * nthr;
+    dst[q] = -1;
+    if (t < nb) {
+      const int s = t / nbs;
+      const int j = t - s * nbs;
+      const int k = j & (Ns - 1);
+      cx<T>* p = buf + s * stride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = p[j + r * nbs];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = mul(v[q][r], twiddle<DIR>(tw, r * k * twstep));
+      }
+      dftR<R, DIR>(v[q]);
+      dst[q] = s * stride + (j - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    if (dst[q] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[q] + r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full in-place FFT of nseq sequences of power-of-two length n in LDS.
+// tw: table of exp(-2 pi i m / twn) with twn a multiple of n.
+template <int DIR, int VPT, typename T>
+__device__ void fft_lds(cx<T>* buf, int n, int nseq, int stride, const cx<T>* __restrict__ tw,
+                        int twn, int tid, int nthr) {
+  const FftPlan p = make_plan(n);
+  int Ns = 1;
+  if (p.n2) {
+    stockham_stage<2, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    Ns *= 2;
+  }
+  for (int i = 0; i < p.n4; ++i) {
+    stockham_stage<4, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    Ns *= 4;
+  }
+  for (int i = 0; i < p.n8; ++i) {
+    stockham_stage<8, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    Ns *= 8;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed order: wave shuffle tree, then the
+// waves' partials in index order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Reduce NV values per thread across the block; result valid in thread 0.
+// scratch: NV * (blockDim/64) doubles of LDS.  is_max[i] selects max vs sum.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV],
+                                             double* scratch) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = is_max[i] ? wave_max(v[i]) : wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) scratch[i * nw + wid] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double a = scratch[i * nw];
+      for (int w = 1; w < nw; ++w) a = is_max[i] ? fmax(a, scratch[i * nw + w]) : a + scratch[i * nw + w];
+      v[i] = a;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace mmk

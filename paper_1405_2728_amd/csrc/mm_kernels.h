@@ -1,0 +1,96 @@
+// Host-callable launchers of the HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmk {
+
+constexpr double kMu0Host = 4.0e-7 * 3.14159265358979323846;
+
+// Minimiser state of one sample, resident in device memory.  Written only
+// by the step-size kernel (one thread) and read by every kernel of the
+// iteration; the host reads it when polling.
+struct MinState {
+  double tau;          // step applied by the update of the current iteration
+  double torque;       // max_i |g_i| / Ms of the last evaluated m_k
+  double energy;       // U(m_k)
+  double eterm[4];     // demag, exchange, anisotropy, Zeeman parts of U(m_k)
+  double ss, sy, yy;   // BB sums of the last evaluation (k >= 1)
+  double best_torque;  // smallest torque of the run (stall detection)
+  double tol;          // stop tolerance on max|g|/Ms
+  double tau0;         // first step
+  long long k;         // updates applied in this run
+  long long best_k;    // k at best_torque
+  long long evals;     // effective-field evaluations in this run
+  long long max_iter;
+  long long stall_iters;  // 0 disables
+  int done;            // 0 running; 1 converged; 2 max_iter; 3 stalled; -1 non-finite
+  int mode;            // 0 minimise with stop rule; 1 forced steps; 2 evaluate only
+  double last_tau;     // tau used by the most recent update (for step info)
+  long long last_k;    // k index of the most recent evaluation
+};
+
+// Gauss-Legendre rules used by the far-field tensor (nodes on [-1, 1]).
+struct GaussRules {
+  double x6[6], w6[6];
+  double x4[4], w4[4];
+  double x3[3], w3[3];
+};
+
+// ---- tensor set-up (FP64) --------------------------------------------------
+void launch_newell_octant(hipStream_t s, double* out, int nx, int ny, int nz, double dx,
+                          double dy, double dz, const GaussRules& gr);
+void launch_embed_thin(hipStream_t s, const double* oct, double* E, int nx, int ny, int nz, int Px,
+                       int Py);
+template <typename T>
+void launch_extract_thin(hipStream_t s, const void* EXY, T* Tt, int M, int nz, int Py);
+void launch_twiddles(hipStream_t s, void* tw, int P, bool single);
+
+// ---- demag passes ------------------------------------------------------------
+// Rows per block chosen by the host: rows_per_block.
+template <typename T>
+void launch_fwd_x(hipStream_t s, const double* in, int in_row_stride, int nx_in, int rows, int ncomp,
+                  int Px, int rows_per_block, void* out, const void* twx, const int* done);
+template <typename T>
+void launch_inv_x(hipStream_t s, const void* in, int rows, int ncomp, int nx_out, int Px,
+                  int rows_per_block, double* out, const void* twx, const int* done);
+template <typename T>
+void launch_fft_cols(hipStream_t s, void* data, int n, int nseq, const void* tw);
+template <typename T>
+void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt, T scale,
+                    const void* twy, const int* done);
+bool yz_thin_fits(int nz, int Py, bool single);
+
+// ---- local terms, step size, update -----------------------------------------
+struct LocalArgs {
+  const double* m;
+  const double* Hd;
+  double* g;            // in: g_{k-1}; out: g_k (NULL: no g / BB sums)
+  const double* s;      // s_{k-1} (NULL: no BB sums)
+  double* Hout;         // total effective field (NULL: not written)
+  double* Hex_out;      // exchange field (NULL: not written)
+  double* Han_out;      // anisotropy field (NULL: not written)
+  const double* ku_map; // per-cell Ku (NULL: scalar ku)
+  int nx, ny, nz;
+  double cx, cy, cz;    // 2A/(mu0 Ms D^2) per axis
+  double ku, kan;       // scalar Ku; 2/(mu0 Ms)
+  double u[3], H[3];
+  double* partials;     // [nblocks][8]
+  const MinState* st;   // NULL outside the minimiser
+  const int* done;      // NULL outside the minimiser
+};
+constexpr int kLocalThreads = 256;
+constexpr int kNPartial = 8;
+int local_blocks(int N);
+void launch_local(hipStream_t s, const LocalArgs& a);
+void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
+                   double V);
+void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
+                   const MinState* st);
+void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
+                        long long stall_iters, int mode);
+void launch_set_mode(hipStream_t s, MinState* st, int mode);
+void launch_mean(hipStream_t s, const double* m, int N, double* partials, double* out3);
+
+}  // namespace mmk

@@ -1,0 +1,260 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (max-norm over all cells and components, relative to the
+reference's max-norm):
+* FP64 effective field 1e-10: FFT rounding is ~1e-15 log2(N); the near-field
+  Newell closed form in double loses up to ~3e-11 relative to cancellation
+  (the oracle evaluates it in 64-bit-mantissa precision), which enters H
+  scaled by the small tensor entries near the 6-cell switch.
+* mixed (FP32 convolution) effective field 1e-5 (single-precision FFTs of
+  length ~1e3 give ~1e-6).
+* iterates: the BB map amplifies rounding; 1e-9 after 10 iterations.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fields as of, minimizer as om
+
+pytestmark = pytest.mark.gpu
+
+MU0 = 4e-7 * np.pi
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1405_2728_amd import _build
+    if not os.path.exists(_build.lib_path()):
+        _build.build(verbose=False)
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def make(torch, prec, nx, ny, nz, d, Ms=8e5, A=1.3e-11, Ku=500.0, u=(1, 0, 0), H=(0, 0, 0),
+         ku_map=None):
+    from paper_1405_2728_amd import Context
+    ctx = Context(prec)
+    ctx.set_geometry(0, nx, ny, nz, *d)
+    km = None if ku_map is None else torch.tensor(ku_map, dtype=torch.float64, device="cuda")
+    ctx.set_material(0, Ms, A, Ku, u, km)
+    ctx.set_field(0, H)
+    P = of.Problem(nx, ny, nz, *d, Ms=Ms, A=A, Ku=Ku if ku_map is None else ku_map, u=u, H_ext=H)
+    return ctx, P
+
+
+SHAPES = [
+    ((5, 4, 1), (5e-9, 5e-9, 5e-9)),
+    ((6, 3, 2), (5e-9, 4e-9, 3e-9)),
+    ((7, 5, 3), (2e-9, 3e-9, 2.5e-9)),
+    ((1, 4, 2), (5e-9, 5e-9, 5e-9)),
+    ((4, 1, 2), (5e-9, 5e-9, 5e-9)),
+    ((1, 1, 1), (5e-9, 5e-9, 5e-9)),
+    ((2, 2, 4), (5e-9, 5e-9, 5e-9)),
+    ((33, 17, 4), (5e-9, 5e-9, 5e-9)),
+    ((32, 16, 1), (5e-9, 5e-9, 5e-9)),
+    ((64, 9, 1), (3e-9, 5e-9, 4e-9)),
+    ((13, 40, 2), (5e-9, 5e-9, 5e-9)),
+]
+
+
+@pytest.mark.parametrize("shape,d", SHAPES)
+def test_heff_terms_fp64(torch_cuda, shape, d):
+    torch = torch_cuda
+    nx, ny, nz = shape
+    say("case heff fp64", shape, d)
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    H = (2.3e4, -4e3, 1.1e4)
+    ctx, P = make(torch, "fp64", nx, ny, nz, d, Ku=3e4, u=(0.6, 0.0, 0.8), H=H)
+    m = torch.tensor(m0, device="cuda")
+    Hg = ctx.heff(0, m).cpu().numpy()
+    Ho = P.heff(m0)
+    e = rel(Hg, Ho)
+    say("  H_eff rel err", e)
+    assert e < 1e-10
+    hd, hex_, han = (t.cpu().numpy() for t in ctx.field_terms(0, m))
+    t = P.field_terms(m0)
+    scale = np.max(np.abs(Ho))
+    assert np.max(np.abs(hd - t["demag"])) < 1e-10 * scale
+    assert np.max(np.abs(hex_ - t["exchange"])) < 1e-12 * scale
+    assert np.max(np.abs(han - t["anisotropy"])) < 1e-12 * scale
+    E, terms = ctx.energy(0, m)
+    Eo = P.energy_terms(m0)
+    assert abs(E - sum(Eo)) < 1e-10 * sum(abs(x) for x in Eo)
+    for a, b in zip(terms, Eo):
+        assert abs(a - b) < 1e-10 * sum(abs(x) for x in Eo)
+    ctx.close()
+
+
+def test_heff_ku_map_and_determinism(torch_cuda):
+    torch = torch_cuda
+    nx, ny, nz = 24, 10, 2
+    d = (5e-9,) * 3
+    say("case ku map", (nx, ny, nz))
+    rng = np.random.default_rng(5)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    ku = 500.0 * (1 + 0.1 * rng.standard_normal((nz, ny, nx)))
+    ctx, P = make(torch, "fp64", nx, ny, nz, d, ku_map=ku, H=(1e3, 2e3, 3e3))
+    m = torch.tensor(m0, device="cuda")
+    a = ctx.heff(0, m).cpu().numpy()
+    b = ctx.heff(0, m).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert rel(a, P.heff(m0)) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (100, 50, 2)])
+def test_heff_mixed_precision(torch_cuda, shape):
+    torch = torch_cuda
+    nx, ny, nz = shape
+    d = (5e-9,) * 3
+    say("case heff mixed", shape)
+    rng = np.random.default_rng(7)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    ctx, P = make(torch, "mixed", nx, ny, nz, d, H=(1e4, 0, 0))
+    m = torch.tensor(m0, device="cuda")
+    e = rel(ctx.heff(0, m).cpu().numpy(), P.heff(m0))
+    say("  mixed H_eff rel err", e)
+    assert e < 1e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("start,tol_m,tol_tau", [
+    # near-uniform start (as in the benchmarked loop): moderate BB steps
+    ("noise", 1e-11, 1e-9),
+    # random start: the first BB steps rotate cells by up to ~pi, so the
+    # ~1e-10 relative rounding of the tiny first s and y is amplified
+    ("random", 1e-7, 1e-6),
+])
+def test_iterates_match_oracle(torch_cuda, start, tol_m, tol_tau):
+    torch = torch_cuda
+    nx, ny, nz = 20, 12, 2
+    d = (5e-9,) * 3
+    say("case iterates", start, (nx, ny, nz))
+    rng = np.random.default_rng(11)
+    if start == "random":
+        m0 = synth.random_unit(nx, ny, nz, rng)
+    else:
+        m0 = synth.uniform_with_noise((1, 0.2, 0), nx, ny, nz, 0.05, rng)
+    H = (2e4, 3e3, 0.0)
+    ctx, P = make(torch, "fp64", nx, ny, nz, d, H=H)
+    m = torch.tensor(m0, device="cuda")
+    ref = om.minimize(P, m0, tol=0.0, max_iter=10, record=True)
+    taus, errs = [], []
+    for k in range(10):
+        info = ctx.minimize_step(0, m)
+        taus.append(info["tau"])
+        assert info["k"] == k
+        assert abs(info["torque"] - ref["torques"][k]) < 1e-9 * ref["torques"][k]
+    err = np.max(np.abs(m.cpu().numpy() - ref["m"]))
+    tau_err = np.max(np.abs(np.array(taus) / np.array(ref["taus"]) - 1))
+    say("  10-iterate max diff", err, "tau rel", tau_err)
+    assert err < tol_m
+    assert tau_err < tol_tau
+    ctx.close()
+
+
+def test_minimize_to_tol_cross_stationary(torch_cuda):
+    torch = torch_cuda
+    nx, ny, nz = 16, 8, 1
+    d = (5e-9,) * 3
+    say("case minimize_to_tol", (nx, ny, nz))
+    rng = np.random.default_rng(12)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    ctx, P = make(torch, "fp64", nx, ny, nz, d)
+    m = torch.tensor(m0, device="cuda")
+    r = ctx.minimize_to_tol(0, m, tol=1e-6, max_iter=100000)
+    ref = om.minimize(P, m0, tol=1e-6)
+    say("  gpu iters", r["iters"], "oracle iters", ref["iters"])
+    assert r["converged"] and r["heff_evals"] == r["iters"] + 1
+    mg = m.cpu().numpy()
+    assert om.torque(mg, P.heff(mg), P.Ms) < 1e-6 * 1.0001
+    assert om.torque(ref["m"], P.heff(ref["m"]), P.Ms) < 1e-6
+    # same basin: same state and energy
+    assert np.max(np.abs(mg - ref["m"])) < 1e-3
+    assert abs(r["energy"] - ref["energy"]) < 1e-8 * abs(ref["energy"])
+    ctx.close()
+
+
+def test_workload0_sweep_matches_oracle(torch_cuda):
+    """32x16x1 film, random start, H = 0, 4, ..., 20 mT at 1 degree."""
+    torch = torch_cuda
+    w = synth.workload(0)
+    nx, ny, nz = w["n"]
+    say("case workload 0 sweep")
+    from paper_1405_2728_amd import Context
+    ctx = Context("fp64")
+    ctx.set_geometry(0, nx, ny, nz, *w["d"])
+    ctx.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
+    m = torch.tensor(w["m0"], device="cuda")
+    mavg, iters, rc = ctx.hysteresis_sweep([m], w["fields"], tol=w["tol"])
+    P = of.Problem(nx, ny, nz, *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"])
+    ref = om.sweep(P, w["m0"], w["fields"], tol=w["tol"])
+    say("  gpu iters", iters[0].tolist(), "oracle", ref["iters"].tolist())
+    assert rc == 0 and ref["converged"].all()
+    assert np.max(np.abs(mavg[0] - ref["mavg"])) < 1e-3
+    mg = m.cpu().numpy()
+    P.H_ext = w["fields"][-1]
+    assert om.torque(mg, P.heff(mg), P.Ms) < 1e-6 * 1.0001
+    ctx.close()
+
+
+def test_sp1_size_heff_fp64_and_mixed(torch_cuda):
+    """The benchmarked 400x200x4 film: full comparison with the oracle's
+    FFT convolution."""
+    torch = torch_cuda
+    w = synth.workload(1)
+    nx, ny, nz = w["n"]
+    say("case 400x200x4 heff")
+    H = w["fields"][0]
+    P = of.Problem(nx, ny, nz, *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"], H_ext=H)
+    rng = np.random.default_rng(3)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    Ho = P.heff(m0)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-5)):
+        ctx, _ = make(torch, prec, nx, ny, nz, w["d"], H=H)
+        m = torch.tensor(m0, device="cuda")
+        e = rel(ctx.heff(0, m).cpu().numpy(), Ho)
+        say("  ", prec, "rel err", e)
+        assert e < tol
+        ctx.close()
+
+
+def test_error_paths(torch_cuda):
+    torch = torch_cuda
+    from paper_1405_2728_amd import Context, MMError
+    ctx = Context("fp64")
+    with pytest.raises(MMError) as ei:
+        ctx.set_geometry(0, 64, 64, 64, 1e-9, 1e-9, 1e-9)
+    assert ei.value.code == -6
+    ctx.set_geometry(0, 8, 4, 1, 5e-9, 5e-9, 5e-9)
+    with pytest.raises(MMError) as ei:
+        ctx.heff(0, torch.zeros(3 * 32, dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -5                     # no material yet
+    ctx.set_material(0, 8e5, 1.3e-11, 500.0)
+    m = torch.tensor(synth.random_unit(8, 4, 1, np.random.default_rng(0)), device="cuda")
+    m[0, 0, 1, 1] = float("nan")
+    with pytest.raises(MMError) as ei:
+        ctx.minimize_to_tol(0, m, tol=1e-6, max_iter=100)
+    assert ei.value.code == -4
+    m = torch.tensor(synth.random_unit(8, 4, 1, np.random.default_rng(0)), device="cuda")
+    r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=7)
+    assert r["status"] == 1 and r["iters"] == 7
+    with pytest.raises(ValueError):
+        ctx.heff(0, torch.zeros(5, dtype=torch.float64, device="cuda"))
+    ctx.close()

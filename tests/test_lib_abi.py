@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports every symbol of include/mm.h; host
+logic that needs no GPU (argument validation, support predicate, strings)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1405_2728_amd import _build, _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_build.lib_path()):
+        _build.build(verbose=False)
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mm_set_geometry", "mm_set_material", "mm_set_field", "mm_heff",
+                     "mm_energy", "mm_minimize_step", "mm_minimize_to_tol",
+                     "mm_hysteresis_sweep"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_support_predicate(lib):
+    assert lib.mm_supported(0, 400, 200, 4) == 1       # SP1-like film
+    assert lib.mm_supported(1, 400, 200, 4) == 1
+    assert lib.mm_supported(0, 32, 16, 1) == 1
+    assert lib.mm_supported(0, 256, 128, 2) == 1
+    assert lib.mm_supported(0, 1, 1, 1) == 1
+    assert lib.mm_supported(0, 0, 5, 1) == 0
+    assert lib.mm_supported(0, 10, 10, 0) == 0
+
+
+def test_status_strings(lib):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+        assert lib.mm_strerror(code)
+    assert lib.mm_kernel_name(0) == b"fwd_x"
+    assert lib.mm_kernel_name(99) is None
+
+
+def test_argument_validation_without_gpu(lib):
+    h = C.c_void_p()
+    assert lib.mm_create(None, 0, 1, None) == -1
+    assert lib.mm_create(C.byref(h), 7, 1, None) == -1
+    assert lib.mm_create(C.byref(h), 0, 0, None) == -1
+    assert lib.mm_create(C.byref(h), 0, 2, None) == 0
+    try:
+        assert lib.mm_set_geometry(h, 0, 0, 4, 1, 1e-9, 1e-9, 1e-9) == -1
+        assert lib.mm_set_geometry(h, 5, 4, 4, 1, 1e-9, 1e-9, 1e-9) == -1
+        assert lib.mm_set_geometry(h, 0, 4, 4, 1, -1e-9, 1e-9, 1e-9) == -1
+        assert b"cell sizes" in lib.mm_last_error(h)
+        # calls before a geometry exists are out of order
+        H = (C.c_double * 3)(0.0, 0.0, 0.0)
+        assert lib.mm_set_field(h, 1, H) == -5
+        assert lib.mm_set_material(h, 0, 8e5, 1e-11, 0.0, None, None) == -5
+        assert lib.mm_set_option(h, b"poll_every", 0.0) == -1
+        assert lib.mm_set_option(h, b"no_such_key", 1.0) == -1
+        assert lib.mm_set_option(h, b"poll_every", 8.0) == 0
+        assert lib.mm_set_option(h, b"tau0", -1.0) == -1
+    finally:
+        lib.mm_destroy(h)
+    lib.mm_destroy(None)
