@@ -34,10 +34,20 @@ def parse():
     p.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-iters", type=int, default=20)
+    p.add_argument("--quick", action="store_true",
+                   help="only the timed run (for profilers): no profiled pass, no other "
+                        "precision, no CPU baseline")
+    p.add_argument("--copy-probe", type=float, default=0.0, metavar="MB",
+                   help="run a plain device copy of MB megabytes 5 times and exit "
+                        "(calibration of the memory-traffic counters)")
     return p.parse_args()
 
 
 def run_gpu(prec, steps, warmup, w, profile):
+    """Warm up, then time `steps` iterations.  With `profile` ("all" or a
+    list of kernel names), the library records HIP events around those
+    kernels' launches in the timed region (on the library's stream) and the
+    per-kernel averages are returned."""
     import torch
     from paper_1405_2728_amd import Context
     nx, ny, nz = w["n"]
@@ -49,18 +59,32 @@ def run_gpu(prec, steps, warmup, w, profile):
     ctx.minimize_to_tol(0, m, tol=0.0, max_iter=warmup)
     torch.cuda.synchronize()
     if profile:
-        ctx.profile(True)
+        ctx.profile(profile)
     t0 = time.perf_counter()
     r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = ctx.profile_read() if profile else None
     if profile:
-        ctx.profile(False)
+        ctx.profile(None)
     kb = ctx.kernel_bytes(0)
     ctx.close()
     return {"iters": r["iters"], "evals": r["heff_evals"], "seconds": dt, "prof": prof,
             "bytes": kb, "torque": r["torque"]}
+
+
+def stored_traffic(prec, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<prec>.json), or None if absent or stale."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s.json" % prec)
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        t = json.load(fh)
+    from paper_1405_2728_amd.profiling import source_hash
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(w, iters):
@@ -84,21 +108,41 @@ def main():
         sys.exit(2)
     import torch
     import synth
+    if a.copy_probe > 0:
+        n = int(a.copy_probe * 1e6 / 8)
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 8 * n, "launches": 5}))
+        return
     w = synth.workload(1)
-    main_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=False)
-    prof_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=True)
+    if a.quick:
+        q = run_gpu(a.prec, a.steps, a.warmup, w, profile=False)
+        print(json.dumps({"value": q["iters"] / q["seconds"], "unit": "iters/s",
+                          "precision": a.prec, "steps": a.steps}))
+        return
+    # timed region (no events)
+    main_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=None)
+    # same region with events around every kernel: the per-kernel breakdown
+    all_run = run_gpu(a.prec, a.steps, a.warmup, w, profile="all")
+    prof = all_run["prof"]
+    dom = max(prof, key=lambda k: prof[k][0])
+    # same region with events around the dominant kernel only: its duration
+    dom_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=[dom])
     other = "mixed" if a.prec == "fp64" else "fp64"
-    other_run = run_gpu(other, a.steps, a.warmup, w, profile=False)
+    other_run = run_gpu(other, a.steps, a.warmup, w, profile=None)
+    other_prof = run_gpu(other, a.steps, a.warmup, w, profile="all")["prof"]
 
     ips = main_run["iters"] / main_run["seconds"]
-    # dominant kernel of the profiled pass
-    prof = prof_run["prof"]
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, n = prof[dom]
+    ms, n = dom_run["prof"][dom]
     avg_s = ms / 1e3 / max(n, 1)
-    achieved = prof_run["bytes"][dom] / avg_s / 1e9
-    per_iter_bytes = sum(prof_run["bytes"][k] for k in prof if k != "finish")
-    kernel_ms = {k: (v[0] / max(v[1], 1)) for k, v in prof.items()}
+    achieved = main_run["bytes"][dom] / avg_s / 1e9
+    traffic = stored_traffic(a.prec, dom)
+    per_iter_bytes = sum(main_run["bytes"][k] for k, v in prof.items() if v[1] > 0)
+    kernel_us = {k: 1e3 * v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    oips = other_run["iters"] / other_run["seconds"]
     out = {
         "metric": "minimiser iterations/s (= H_eff evals/s) at 400x200x4",
         "value": ips,
@@ -112,16 +156,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "film 400x200x4 cells of 5 nm, SP1 material, +50 mT at 1 deg, "
-                               "BB midpoint minimiser", "precision": a.prec,
+        "config": {"workload": "film 400x200x4 cells of 5 nm (Standard Problem 1 stand-in), "
+                               "BB midpoint minimiser, +50 mT at 1 deg", "precision": a.prec,
                    "padded_grid": [1024, 512, 4]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0,
-                     "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
-                     "avg_kernel_us": avg_s * 1e6},
-        "iteration_model": {"bytes_per_iter": per_iter_bytes,
-                            "GBps_per_iter": per_iter_bytes * ips / 1e9,
-                            "kernel_avg_us": {k: 1e3 * v for k, v in kernel_ms.items()}},
-        other: {"value": other_run["iters"] / other_run["seconds"], "unit": "iters/s"},
+                     "unit": "GB/s", "frac": achieved / 8000.0,
+                     "traffic": traffic, "avg_kernel_us": avg_s * 1e6,
+                     "algorithmic_bytes": main_run["bytes"][dom]},
+        "iteration": {"model_bytes": per_iter_bytes,
+                      "model_GBps": per_iter_bytes * ips / 1e9,
+                      "model_frac_of_8TBps": per_iter_bytes * ips / 8e12,
+                      "kernel_avg_us_all_timed": kernel_us},
+        other: {"value": oips, "unit": "iters/s",
+                "speedup_vs_" + a.prec: oips / ips,
+                "kernel_avg_us_all_timed": {k: 1e3 * v[0] / max(v[1], 1)
+                                            for k, v in other_prof.items() if v[1] > 0}},
     }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters)

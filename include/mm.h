@@ -142,13 +142,14 @@ int mm_field_terms(mm_ctx* ctx, int sample, const double* m, double* H_demag,
 int mm_energy(mm_ctx* ctx, int sample, const double* m, double* E, double* terms4);
 
 /* One iteration of the minimiser on m (device [3][N], updated in place):
- * H_eff(m_k), g_k, the stop test, the step size of eq. (12) and the update
- * of eq. (7).  Continues the current run (state kept in the context; call
- * mm_reset before starting on a different m).  Returns MM_OK when the
- * update was applied, MM_OK with info->torque < tol semantics left to the
- * caller (this call applies no stop rule), MM_ENONFINITE on NaN/Inf.
- * info (host, may be NULL) receives tau, torque and energy of m_k.
- * Synchronises when info is not NULL. */
+ * H_eff(m_k), g_k, the step size of eq. (12) and the update of eq. (7).
+ * No stop rule is applied: the update is always performed (the caller may
+ * inspect info->torque).  Continues the current run (state kept in the
+ * context; call mm_reset before starting on a different m).  Returns MM_OK,
+ * or MM_ENONFINITE when the torque or energy of m_k is not finite (m is
+ * then left unchanged).  info (host, may be NULL) receives tau (the step
+ * applied), torque and energy of m_k and k.  Synchronises when info is not
+ * NULL. */
 int mm_minimize_step(mm_ctx* ctx, int sample, double* m, mm_step_info* info);
 
 /* Run the minimiser from m (device [3][N], updated in place) until
@@ -188,12 +189,15 @@ int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
 int mm_supported(int prec, int nx, int ny, int nz);
 
 /* Per-kernel timing with HIP events on the context's stream.
- * mm_profile(ctx, 1) starts recording (and clears totals), 0 stops.
- * mm_profile_read(ctx, id, &ms, &launches) reads the accumulated time of
- * kernel id (synchronises).  mm_kernel_name(id) names it (NULL past the
- * last id).  mm_kernel_bytes(ctx, sample, id, &bytes) gives that kernel's
- * algorithmic bytes per launch (compulsory reads + writes of its pass). */
-int mm_profile(mm_ctx* ctx, int enable);
+ * mm_profile(ctx, mask) records an event pair around every launch of each
+ * kernel whose bit is set in mask (bit k = kernel id k; 0 stops recording)
+ * and clears the totals.  Events add a small gap per timed launch, so time
+ * only the kernels of interest.  mm_profile_read(ctx, id, &ms, &launches)
+ * reads the accumulated time of kernel id (synchronises).
+ * mm_kernel_name(id) names it (NULL past the last id).
+ * mm_kernel_bytes(ctx, sample, id, &bytes) gives that kernel's algorithmic
+ * bytes per launch in a minimiser iteration (compulsory reads + writes). */
+int mm_profile(mm_ctx* ctx, int mask);
 int mm_profile_read(mm_ctx* ctx, int kernel_id, double* total_ms, int64_t* launches);
 const char* mm_kernel_name(int kernel_id);
 int mm_kernel_bytes(mm_ctx* ctx, int sample, int kernel_id, double* bytes);

@@ -188,8 +188,22 @@ class Context:
         return e.value, i.value
 
     # -- timing ---------------------------------------------------------------
-    def profile(self, enable):
-        self._check(self._lib.mm_profile(self._h, 1 if enable else 0))
+    def profile(self, kernels=None):
+        """Time the named kernels (None or [] stops; "all" times every
+        kernel) with HIP events."""
+        mask = 0
+        if kernels == "all":
+            mask = (1 << 30) - 1
+        elif kernels:
+            k = 0
+            while True:
+                name = self._lib.mm_kernel_name(k)
+                if name is None:
+                    break
+                if name.decode() in kernels:
+                    mask |= 1 << k
+                k += 1
+        self._check(self._lib.mm_profile(self._h, mask))
 
     def profile_read(self):
         out = {}

@@ -15,16 +15,18 @@ using namespace mmk;
 
 namespace {
 
-constexpr int kNumKernels = 6;
-const char* const kKernelNames[kNumKernels] = {"fwd_x", "yz_thin", "inv_x", "local", "finish",
-                                               "update"};
-enum { KID_FWD = 0, KID_YZ = 1, KID_INV = 2, KID_LOCAL = 3, KID_FINISH = 4, KID_UPDATE = 5 };
+constexpr int kNumKernels = 4;
+// xf: pending update + forward x FFT; yz_thin: y FFT, tensor product, inverse
+// y FFT; xil: inverse x FFT + local terms + sums + step choice; update:
+// stand-alone update (single-step calls only)
+const char* const kKernelNames[kNumKernels] = {"xf", "yz_thin", "xil", "update"};
+enum { KID_XF = 0, KID_YZ = 1, KID_XIL = 2, KID_UPDATE = 3 };
 
 struct Sample {
   bool has_geom = false, has_mat = false;
   int nx = 0, ny = 0, nz = 0, N = 0;
   double dx = 0, dy = 0, dz = 0, V = 0;
-  int Px = 0, Py = 0, M = 0, Rx = 1;
+  int Px = 0, Py = 0, M = 0, R3 = 1, nb3 = 0, tstride = 0;
   double Ms = 0, A = 0, Ku = 0, u[3] = {1, 0, 0}, H[3] = {0, 0, 0};
   double* ku_map = nullptr;
   void* Tt = nullptr;
@@ -60,7 +62,7 @@ struct mm_ctx {
   int poll_every = 32;
   long long stall_iters = 500;
   int use_graph = 0;
-  bool prof = false;
+  unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   double prof_ms[kNumKernels] = {0};
@@ -173,13 +175,13 @@ struct Timer {
   int id;
   hipEvent_t a = nullptr;
   Timer(mm_ctx* ctx, int kid) : c(ctx), id(kid) {
-    if (c->prof) {
+    if (c->prof & (1u << kid)) {
       a = take_event(c);
       (void)hipEventRecord(a, c->stream);
     }
   }
   ~Timer() {
-    if (c->prof) {
+    if (c->prof & (1u << id)) {
       hipEvent_t b = take_event(c);
       (void)hipEventRecord(b, c->stream);
       c->prof_pending.push_back({id, a, b});
@@ -242,8 +244,8 @@ int build_tensor(mm_ctx* c, Sample& s) {
   if (R < 1) R = 1;
   launch_fwd_x<double>(st, E, s.Px, s.Px, s.nz * s.Py, 6, s.Px, R, EX, twx64, nullptr);
   launch_fft_cols<double>(st, EX, s.Py, (M + 1) * 6 * s.nz, twy64);
-  if (single(c)) launch_extract_thin<float>(st, EX, (float*)s.Tt, M, s.nz, s.Py);
-  else launch_extract_thin<double>(st, EX, (double*)s.Tt, M, s.nz, s.Py);
+  if (single(c)) launch_extract_thin<float>(st, EX, (float*)s.Tt, M, s.nz, s.Py, s.tstride);
+  else launch_extract_thin<double>(st, EX, (double*)s.Tt, M, s.nz, s.Py, s.tstride);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   cleanup();
@@ -253,51 +255,23 @@ int build_tensor(mm_ctx* c, Sample& s) {
 
 // ---- one effective-field evaluation ----------------------------------------
 struct EvalOut {
-  double* Hd = nullptr;       // demag output (NULL: internal buffer)
+  double* Hd = nullptr;       // demag output (NULL: not written)
   double* H = nullptr;        // total field
   double* Hex = nullptr;
   double* Han = nullptr;
-  bool iterate = false;       // minimiser iteration: g, BB sums, state
-  MinState* st = nullptr;     // state for finish (NULL: no finish)
+  bool iterate = false;       // minimiser iteration: pending update, g, BB sums
+  MinState* st_fin = nullptr; // state the sums are reduced into (NULL: none)
 };
 
-void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
-  hipStream_t st = c->stream;
-  const int* done = o.iterate ? &o.st->done : nullptr;
-  const int rows = s.nz * s.ny;
-  double* Hd = o.Hd ? o.Hd : s.Hd;
-  {
-    Timer t(c, KID_FWD);
-    if (single(c))
-      launch_fwd_x<float>(st, m, s.nx, s.nx, rows, 3, s.Px, s.Rx, s.spec, s.twx, done);
-    else
-      launch_fwd_x<double>(st, m, s.nx, s.nx, rows, 3, s.Px, s.Rx, s.spec, s.twx, done);
-  }
-  {
-    Timer t(c, KID_YZ);
-    const double scale = -s.Ms / ((double)s.M * (double)s.Py);
-    if (single(c))
-      launch_yz_thin<float>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const float*)s.Tt, (float)scale,
-                            s.twy, done);
-    else
-      launch_yz_thin<double>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const double*)s.Tt, scale, s.twy,
-                             done);
-  }
-  {
-    Timer t(c, KID_INV);
-    if (single(c))
-      launch_inv_x<float>(st, s.spec, rows, 3, s.nx, s.Px, s.Rx, Hd, s.twx, done);
-    else
-      launch_inv_x<double>(st, s.spec, rows, 3, s.nx, s.Px, s.Rx, Hd, s.twx, done);
-  }
+LocalArgs local_args(const Sample& s) {
   LocalArgs a;
-  a.m = m;
-  a.Hd = Hd;
-  a.g = o.iterate ? s.g : nullptr;
-  a.s = o.iterate ? s.s : nullptr;
-  a.Hout = o.H;
-  a.Hex_out = o.Hex;
-  a.Han_out = o.Han;
+  a.m = nullptr;
+  a.Hd = nullptr;
+  a.g = nullptr;
+  a.s = nullptr;
+  a.Hout = nullptr;
+  a.Hex_out = nullptr;
+  a.Han_out = nullptr;
   a.ku_map = s.ku_map;
   a.nx = s.nx;
   a.ny = s.ny;
@@ -313,25 +287,57 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
     a.H[q] = s.H[q];
   }
   a.partials = s.partials;
-  a.st = o.iterate ? o.st : nullptr;
+  a.st = nullptr;
+  a.done = nullptr;
+  return a;
+}
+
+// m is updated in place when o.iterate and an update is pending.
+void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
+  hipStream_t st = c->stream;
+  MinState* mst = o.iterate ? s.st : nullptr;
+  const int* done = mst ? &mst->done : nullptr;
+  double* mm = const_cast<double*>(m);
+  {
+    Timer t(c, KID_XF);
+    if (single(c))
+      launch_xf<float>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, s.R3, s.spec, s.twx);
+    else
+      launch_xf<double>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, s.R3, s.spec, s.twx);
+  }
+  {
+    Timer t(c, KID_YZ);
+    const double scale = -s.Ms / ((double)s.M * (double)s.Py);
+    if (single(c))
+      launch_yz_thin<float>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const float*)s.Tt, s.tstride,
+                            (float)scale, s.twy, done);
+    else
+      launch_yz_thin<double>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const double*)s.Tt, s.tstride,
+                             scale, s.twy, done);
+  }
+  LocalArgs a = local_args(s);
+  a.m = m;
+  a.g = o.iterate ? s.g : nullptr;
+  a.s = o.iterate ? s.s : nullptr;
+  a.Hout = o.H;
+  a.Hex_out = o.Hex;
+  a.Han_out = o.Han;
+  a.st = mst;
   a.done = done;
   {
-    Timer t(c, KID_LOCAL);
-    launch_local(st, a);
-  }
-  if (o.st) {
-    Timer t(c, KID_FINISH);
-    launch_finish(st, s.partials, s.nblk, o.st, s.Ms, s.V);
+    Timer t(c, KID_XIL);
+    if (single(c))
+      launch_xil<float>(st, s.spec, a, s.Px, s.R3, o.Hd, o.st_fin, s.Ms, s.V, s.twx);
+    else
+      launch_xil<double>(st, s.spec, a, s.Px, s.R3, o.Hd, o.st_fin, s.Ms, s.V, s.twx);
   }
 }
 
 void enqueue_iteration(mm_ctx* c, Sample& s, double* m) {
   EvalOut o;
   o.iterate = true;
-  o.st = s.st;
+  o.st_fin = s.st;
   enqueue_eval(c, s, m, o);
-  Timer t(c, KID_UPDATE);
-  launch_update(c->stream, m, s.g, s.s, s.N, s.st);
 }
 
 double tau0_of(const mm_ctx* c, const Sample& s) { return c->tau0 > 0 ? c->tau0 : 1e-3 / s.Ms; }
@@ -444,17 +450,14 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.Py = next_pow2(2 * ny - 1);
   s.M = s.Px / 2;
   const bool sp = single(c);
-  const int Rt = sp ? 16 : 8;
-  int R = 8192 / s.M;
-  if (R > Rt) R = Rt;
-  if (R < 1) R = 1;
-  if (R > nz * ny) R = nz * ny;
-  s.Rx = R;
+  s.R3 = rows_per_block(s.M, ny, sp);
+  s.nb3 = nz * ((ny + s.R3 - 1) / s.R3);
   const size_t creal = sp ? sizeof(float) : sizeof(double);
-  const size_t nT = (size_t)(s.M + 1) * nz * (s.Py / 2 + 1) * 6;
+  s.tstride = thin_tensor_stride(nz, s.Py, sp);
+  const size_t nT = (size_t)(s.M + 1) * s.tstride;
   const size_t nspec = (size_t)(s.M + 1) * 3 * nz * ny;
   s.nblk = local_blocks(s.N);
-  const size_t npart = (size_t)(s.nblk > 1 ? s.nblk : 1) * kNPartial;
+  const size_t npart = (size_t)(s.nblk > s.nb3 ? s.nblk : s.nb3) * kNPartial;
   bool ok = hipMalloc(&s.Tt, nT * creal) == hipSuccess &&
             hipMalloc(&s.spec, nspec * 2 * creal) == hipSuccess &&
             hipMalloc(&s.twx, (size_t)s.Px * 2 * creal) == hipSuccess &&
@@ -473,6 +476,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
     (void)hipGetLastError();
     return fail(c, MM_ENOMEM, "device allocation failed");
   }
+  HIPCHK(c, hipMemsetAsync(s.Tt, 0, nT * creal, c->stream));
   HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * sizeof(double), c->stream));
   launch_twiddles(c->stream, s.twx, s.Px, sp);
@@ -577,7 +581,7 @@ int mm_energy(mm_ctx* c, int sample, const double* m, double* E, double* terms4)
   Sample& s = c->smp[sample];
   launch_reset_state(c->stream, s.st_eval, 0.0, 0.0, 0, 0, 2);
   EvalOut o;
-  o.st = s.st_eval;
+  o.st_fin = s.st_eval;
   enqueue_eval(c, s, m, o);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(s.st_host, s.st_eval, sizeof(MinState), hipMemcpyDeviceToHost, c->stream));
@@ -597,6 +601,11 @@ int mm_minimize_step(mm_ctx* c, int sample, double* m, mm_step_info* info) {
   Sample& s = c->smp[sample];
   launch_set_mode(c->stream, s.st, 1);
   enqueue_iteration(c, s, m);
+  {
+    Timer t(c, KID_UPDATE);
+    launch_update(c->stream, m, s.g, s.s, s.N, s.st);
+  }
+  launch_clear_pending(c->stream, s.st);
   HIPCHK(c, hipGetLastError());
   s.evals_total += 1;
   s.iters_total += 1;
@@ -691,10 +700,10 @@ int mm_counters(mm_ctx* c, int sample, int64_t* heff_evals, int64_t* iters) {
   return MM_OK;
 }
 
-int mm_profile(mm_ctx* c, int enable) {
-  if (!c) return MM_EINVAL;
+int mm_profile(mm_ctx* c, int mask) {
+  if (!c || mask < 0) return MM_EINVAL;
   prof_collect(c);
-  c->prof = enable != 0;
+  c->prof = (unsigned)mask & ((1u << kNumKernels) - 1u);
   if (c->prof)
     for (int k = 0; k < kNumKernels; ++k) {
       c->prof_ms[k] = 0;
@@ -724,15 +733,14 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
   const double sr = single(c) ? 4.0 : 8.0;
   const double N3 = 3.0 * s.N * 8.0;                                  // one [3][N] double array
   const double spec = (double)(s.M + 1) * 3 * s.nz * s.ny * 2 * sr;   // spectrum A
-  const double tens = (double)(s.M + 1) * s.nz * (s.Py / 2 + 1) * 6 * sr;
+  const double tens = (double)(s.M + 1) * s.tstride * sr;
+  const double ku = s.ku_map ? s.N * 8.0 : 0.0;
   double b = 0;
   switch (id) {
-    case KID_FWD: b = N3 + spec; break;
-    case KID_YZ: b = 2 * spec + tens; break;
-    case KID_INV: b = spec + N3; break;
-    case KID_LOCAL: b = 5 * N3 + (s.ku_map ? s.N * 8.0 : 0.0); break;  // m, Hd, g, s in; g out
-    case KID_FINISH: b = (double)s.nblk * kNPartial * 8.0; break;
-    case KID_UPDATE: b = 4 * N3; break;                                 // m, g in; m, s out
+    case KID_XF: b = 4 * N3 + spec; break;          // m, g in; m, s out; spectrum out
+    case KID_YZ: b = 2 * spec + tens; break;        // spectrum in/out; tensor in
+    case KID_XIL: b = spec + 4 * N3 + ku; break;    // spectrum, m, g, s in; g out
+    case KID_UPDATE: b = 4 * N3; break;             // m, g in; m, s out
   }
   *bytes = b;
   return MM_OK;

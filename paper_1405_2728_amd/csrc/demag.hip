@@ -8,16 +8,19 @@
 // Passes per evaluation:
 //   fwd_x   rows of m (real, nx values, zero padded to Px) -> half-length
 //           complex FFT (M = Px/2 points, even/odd samples packed as re/im)
-//           -> spectrum X[0..M] written as A[kx][c][z][y]
+//           -> spectrum X[0..M] written as A[kx][z][y][c]
 //   yz_thin one block per kx: y-FFT of the 3*nz columns (zero padded to Py),
 //           symmetric 3x3 tensor times vector with the z convolution,
 //           inverse y-FFT, keep ny rows.  The block of kx = 0 also carries
 //           kx = M: both columns are spectra of real data, packed as
 //           re + i*im and separated by Hermitian symmetry in ky.
-//   inv_x   A[kx][c][z][y] -> half-length inverse -> H_d rows (double)
+//   inv_x   A[kx][z][y][c] -> half-length inverse -> H_d rows (double)
+//   yz_wave as yz_thin, with register-resident wave FFTs (one wave per z
+//           layer, Py = 64..512) and one block per column kx = 0..M
 // The factor -Ms/(M Py) of the inverse transforms is applied in yz_thin.
 #include "mm_device.h"
 #include "mm_kernels.h"
+#include "mm_wfft.h"
 
 namespace mmk {
 
@@ -160,8 +163,8 @@ __device__ __forceinline__ void tensor_apply_z(const T* __restrict__ Tk, int nk,
 
 template <typename T, int VPT, int NZ>
 __global__ void __launch_bounds__(512)
-k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt, T scale,
-          const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt, int tstride,
+          T scale, const cx<T>* __restrict__ twy, const int* __restrict__ done) {
   if (done != nullptr && *done != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
@@ -174,15 +177,16 @@ k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt
     const int col = idx / Py, y = idx - col * Py;
     cx<T> v = mk(T(0), T(0));
     if (y < ny) {
-      if (kx == 0) v = mk(A[(size_t)col * ny + y].x, A[(size_t)M * slab + (size_t)col * ny + y].x);
-      else v = A[(size_t)kx * slab + (size_t)col * ny + y];
+      const size_t e = ((size_t)(col % NZ) * ny + y) * 3 + col / NZ;   // [z][y][c]
+      if (kx == 0) v = mk(A[e].x, A[(size_t)M * slab + e].x);
+      else v = A[(size_t)kx * slab + e];
     }
     buf[col * S + y] = v;
   }
   __syncthreads();
   fft_lds<-1, VPT>(buf, Py, nseq, S, twy, Py, tid, nthr);
   const int nk = (Py >> 1) + 1;
-  const size_t tslab = (size_t)NZ * nk * 6;
+  const size_t tslab = (size_t)tstride;
   if (kx != 0) {
     const T* Tk = Tt + (size_t)kx * tslab;
     for (int ky = tid; ky < Py; ky += nthr) {
@@ -237,12 +241,153 @@ k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt
   for (int idx = tid; idx < nseq * ny; idx += nthr) {
     const int col = idx / ny, y = idx - col * ny;
     const cx<T> v = buf[col * S + y];
+    const size_t e = ((size_t)(col % NZ) * ny + y) * 3 + col / NZ;
     if (kx == 0) {
-      A[(size_t)col * ny + y] = mk(v.x, T(0));
-      A[(size_t)M * slab + (size_t)col * ny + y] = mk(v.y, T(0));
+      A[e] = mk(v.x, T(0));
+      A[(size_t)M * slab + e] = mk(v.y, T(0));
     } else {
-      A[(size_t)kx * slab + (size_t)col * ny + y] = v;
+      A[(size_t)kx * slab + e] = v;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y-FFT, tensor product with z convolution, inverse y-FFT; wave FFT version.
+// Block = NZ wavefronts, wave z owns layer z (three components); block kx
+// handles column kx in 0..M (the real-input columns kx = 0 and kx = M are
+// ordinary columns here; their imaginary parts vanish and are stored as 0).
+// Lane g holds the frequencies ky = wfft_freq(g, d), d < 8.  The tensor slab
+// of the column is copied to LDS with direct global-to-LDS loads while the
+// forward transforms run; the z convolution exchanges two slots d at a time
+// through LDS.
+// LDS: [tensor slab, padded to 1 KiB] [transposes | exchange buffer].
+// ---------------------------------------------------------------------------
+template <typename T, int VL, int NZ, bool HALF>
+__global__ void __launch_bounds__(64 * NZ, 2)
+k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int tstride, T scale,
+          const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+  if (done != nullptr && *done != 0) return;
+  constexpr int n = 64 * VL;
+  constexpr int NG = 8 * VL;
+  constexpr int DC = 2;                       // slots exchanged per round
+  constexpr int nk = n / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tl_bytes = ((tstride * (int)sizeof(T) + 1023) / 1024) * 1024;
+  T* tl = reinterpret_cast<T*>(smem);
+  cx<T>* sm = reinterpret_cast<cx<T>*>(smem + tl_bytes);
+  const int lane = threadIdx.x & 63;
+  const int z = threadIdx.x >> 6;
+  cx<T>* tbuf = sm + z * wfft_buf<VL, HALF>();   // wave-private transpose buffer
+  cx<T>* xbuf = sm;                              // exchange buffer [z][c][DC][64]
+  const int kx = blockIdx.x;
+  const size_t slab = (size_t)3 * NZ * ny;
+  cx<T>* Ak = A + (size_t)kx * slab;
+  // column loads (three components of layer z), one component ahead
+  cx<T> F[3][8];
+  cx<T> xin[2][VL];
+#pragma unroll
+  for (int r = 0; r < VL; ++r) {
+    const int y = lane + 64 * r;
+    xin[0][r] = y < ny ? Ak[((size_t)z * ny + y) * 3 + 0] : mk(T(0), T(0));
+  }
+  // tensor slab -> LDS, 16 bytes per lane, no registers involved
+  {
+    const int nchunk = tstride * (int)sizeof(T) / 16;
+    const unsigned char* src = reinterpret_cast<const unsigned char*>(Tt + (size_t)kx * tstride);
+    for (int base = z * 64; base < nchunk; base += NZ * 64) {
+      const int ch = min(base + lane, nchunk - 1);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src + (size_t)ch * 16),
+          (__attribute__((address_space(3))) void*)(smem + (size_t)base * 16), 16, 0, 0);
+    }
+  }
+  // forward transforms
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < 2) {
+#pragma unroll
+      for (int r = 0; r < VL; ++r) {
+        const int y = lane + 64 * r;
+        xin[(c + 1) & 1][r] = y < ny ? Ak[((size_t)z * ny + y) * 3 + c + 1] : mk(T(0), T(0));
+      }
+    }
+    wfft_forward<T, VL, HALF>(xin[c & 1], F[c], tbuf, twy, lane);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // tensor copy complete (this wave's part)
+  __syncthreads();                 // ... and every wave's; transposes done
+  if constexpr (NZ == 1) {
+    if (lane < NG) {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int ky = wfft_freq<VL>(lane, d);
+        const bool neg = ky > n / 2;
+        const int kyp = neg ? n - ky : ky;
+        const T sy = neg ? T(-1) : T(1);
+        const T* t = tl + kyp * 6;
+        const T xx = t[0], yy = t[1], zz = t[2], xy = t[3] * sy;
+        const cx<T> fx = F[0][d], fy = F[1][d], fz = F[2][d];
+        F[0][d] = scl(add(scl(fx, xx), scl(fy, xy)), scale);
+        F[1][d] = scl(add(scl(fx, xy), scl(fy, yy)), scale);
+        F[2][d] = scl(fz, zz * scale);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int d0 = 0; d0 < 8; d0 += DC) {
+      if (lane < NG) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int dl = 0; dl < DC; ++dl) xbuf[((z * 3 + c) * DC + dl) * 64 + lane] = F[c][d0 + dl];
+      }
+      __syncthreads();
+      if (lane < NG) {
+#pragma unroll
+        for (int dl = 0; dl < DC; ++dl) {
+          const int ky = wfft_freq<VL>(lane, d0 + dl);
+          const bool neg = ky > n / 2;
+          const int kyp = neg ? n - ky : ky;
+          const T sy = neg ? T(-1) : T(1);
+          cx<T> h0 = mk(T(0), T(0)), h1 = h0, h2 = h0;
+#pragma unroll 1
+          for (int zp = 0; zp < NZ; ++zp) {
+            const int dz = z - zp;
+            const int dzp = dz < 0 ? -dz : dz;
+            const T sz = dz < 0 ? T(-1) : T(1);
+            const T* t = tl + (dzp * nk + kyp) * 6;
+            const T xx = t[0], yy = t[1], zz = t[2];
+            const T xy = t[3] * sy, xz = t[4] * sz, yz = t[5] * sy * sz;
+            const cx<T> fx = xbuf[((zp * 3 + 0) * DC + dl) * 64 + lane];
+            const cx<T> fy = xbuf[((zp * 3 + 1) * DC + dl) * 64 + lane];
+            const cx<T> fz = xbuf[((zp * 3 + 2) * DC + dl) * 64 + lane];
+            const cx<T> ifx = rot90<1>(fx), ify = rot90<1>(fy), ifz = rot90<1>(fz);
+            h0 = add(h0, add(add(scl(fx, xx), scl(fy, xy)), scl(ifz, xz)));
+            h1 = add(h1, add(add(scl(fx, xy), scl(fy, yy)), scl(ifz, yz)));
+            h2 = add(h2, add(add(scl(ifx, xz), scl(ify, yz)), scl(fz, zz)));
+          }
+          F[0][d0 + dl] = scl(h0, scale);
+          F[1][d0 + dl] = scl(h1, scale);
+          F[2][d0 + dl] = scl(h2, scale);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // inverse transforms and store of the ny kept rows
+  const bool real_col = (kx == 0 || kx == M);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<T> xo[VL];
+    wfft_inverse<T, VL, HALF>(F[c], xo, tbuf, twy, lane);
+#pragma unroll
+    for (int r = 0; r < VL; ++r) {
+      const int y = lane + 64 * r;
+      if (y < ny) Ak[((size_t)z * ny + y) * 3 + c] = real_col ? mk(xo[r].x, T(0)) : xo[r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -339,8 +484,8 @@ bool yz_thin_fits(int nz, int Py, bool single) {
 }
 
 template <typename T, int NZ>
-static void yz_dispatch(hipStream_t s, void* A, int ny, int Py, int M, const T* Tt, T scale,
-                        const void* twy, const int* done) {
+static void yz_dispatch(hipStream_t s, void* A, int ny, int Py, int M, const T* Tt, int tstride,
+                        T scale, const void* twy, const int* done) {
   const long long vals = 3LL * NZ * Py;
   const size_t lds = (size_t)vals * sizeof(cx<T>);
   dim3 grid(M);
@@ -348,23 +493,58 @@ static void yz_dispatch(hipStream_t s, void* A, int ny, int Py, int M, const T* 
     auto k = k_yz_thin<T, 16, NZ>;
     set_lds(k, lds);
     hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 16)), lds, s, (cx<T>*)A, ny, Py, M, Tt,
-                       scale, (const cx<T>*)twy, done);
+                       tstride, scale, (const cx<T>*)twy, done);
   } else {
     auto k = k_yz_thin<T, 32, NZ>;
     set_lds(k, lds);
     hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 32)), lds, s, (cx<T>*)A, ny, Py, M, Tt,
-                       scale, (const cx<T>*)twy, done);
+                       tstride, scale, (const cx<T>*)twy, done);
   }
 }
 
-template <typename T>
-void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt, T scale,
-                    const void* twy, const int* done) {
+template <typename T, int VL, int NZ>
+static void yz_wave_dispatch(hipStream_t s, void* A, int ny, int M, const T* Tt, int tstride,
+                             T scale, const void* twy, const int* done) {
+  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;     // keep two blocks per CU in FP64
+  const size_t ex = (size_t)NZ * 3 * 2 * 64;           // exchange buffer
+  const size_t tr = (size_t)NZ * wfft_buf<VL, HALF>(); // transpose buffers
+  const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
+  const size_t lds = tl + (ex > tr ? ex : tr) * sizeof(cx<T>);
+  auto k = k_yz_wave<T, VL, NZ, HALF>;
+  set_lds(k, lds);
+  hipLaunchKernelGGL(k, dim3(M + 1), dim3(64 * NZ), lds, s, (cx<T>*)A, ny, M, Tt, tstride, scale,
+                     (const cx<T>*)twy, done);
+}
+
+template <typename T, int VL>
+static void yz_wave_nz(hipStream_t s, void* A, int nz, int ny, int M, const T* Tt, int tstride,
+                       T scale, const void* twy, const int* done) {
   switch (nz) {
-    case 1: yz_dispatch<T, 1>(s, A, ny, Py, M, Tt, scale, twy, done); break;
-    case 2: yz_dispatch<T, 2>(s, A, ny, Py, M, Tt, scale, twy, done); break;
-    case 3: yz_dispatch<T, 3>(s, A, ny, Py, M, Tt, scale, twy, done); break;
-    default: yz_dispatch<T, 4>(s, A, ny, Py, M, Tt, scale, twy, done); break;
+    case 1: yz_wave_dispatch<T, VL, 1>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
+    case 2: yz_wave_dispatch<T, VL, 2>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
+    case 3: yz_wave_dispatch<T, VL, 3>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
+    default: yz_wave_dispatch<T, VL, 4>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
+  }
+}
+
+bool yz_wave_ok(int nz, int Py) { return nz >= 1 && nz <= 4 && Py >= 64 && Py <= 512; }
+
+template <typename T>
+void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt,
+                    int tstride, T scale, const void* twy, const int* done) {
+  if (yz_wave_ok(nz, Py)) {
+    switch (Py) {
+      case 64: yz_wave_nz<T, 1>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 128: yz_wave_nz<T, 2>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 256: yz_wave_nz<T, 4>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      default: yz_wave_nz<T, 8>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+    }
+  }
+  switch (nz) {
+    case 1: yz_dispatch<T, 1>(s, A, ny, Py, M, Tt, tstride, scale, twy, done); break;
+    case 2: yz_dispatch<T, 2>(s, A, ny, Py, M, Tt, tstride, scale, twy, done); break;
+    case 3: yz_dispatch<T, 3>(s, A, ny, Py, M, Tt, tstride, scale, twy, done); break;
+    default: yz_dispatch<T, 4>(s, A, ny, Py, M, Tt, tstride, scale, twy, done); break;
   }
 }
 
@@ -381,9 +561,9 @@ template void launch_inv_x<double>(hipStream_t, const void*, int, int, int, int,
 template void launch_inv_x<float>(hipStream_t, const void*, int, int, int, int, int, double*,
                                   const void*, const int*);
 template void launch_fft_cols<double>(hipStream_t, void*, int, int, const void*);
-template void launch_yz_thin<double>(hipStream_t, void*, int, int, int, int, const double*, double,
-                                     const void*, const int*);
-template void launch_yz_thin<float>(hipStream_t, void*, int, int, int, int, const float*, float,
+template void launch_yz_thin<double>(hipStream_t, void*, int, int, int, int, const double*, int,
+                                     double, const void*, const int*);
+template void launch_yz_thin<float>(hipStream_t, void*, int, int, int, int, const float*, int, float,
                                     const void*, const int*);
 
 }  // namespace mmk

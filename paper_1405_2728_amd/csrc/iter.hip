@@ -1,0 +1,565 @@
+// Fused x passes of one minimiser iteration (thin-film path).
+//
+//   k_xf   pending midpoint update of eq. (7) on R rows (all three
+//          components), s = m+ - m, then the forward half-length real FFT
+//          along x of the updated rows into the spectrum A[kx][z][y][c].
+//   k_xil  inverse x transform of R rows (all three components) -> H_d, then
+//          the local terms, g = m x (m x H) (eq. (8)), the BB sums and the
+//          energy sums of the rows (eq. (12), Sec. 2); the last block to
+//          finish reduces the per-block sums in a fixed order and applies the
+//          stop rule and the alternating step choice.
+// Block b works on rows (z, y0 .. y0+R-1) with the XCD-contiguous mapping
+// of xcd_remap so that neighbouring row groups share L2.
+#include "mm_iter.h"
+#include "mm_wfft.h"
+
+namespace mmk {
+
+template <typename T, int VPT>
+__global__ void __launch_bounds__(512)
+k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
+     const MinState* __restrict__ st, int nx, int ny, int nz, int Px, int R,
+     cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
+  bool upd = false;
+  double tau = 0.0;
+  if (st != nullptr) {
+    if (st->done != 0) return;
+    upd = st->pending != 0;
+    tau = st->last_tau;
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+  const int M = Px >> 1;
+  const int nyb = (ny + R - 1) / R;
+  const int nb = nz * nyb;
+  const int L = xcd_remap(blockIdx.x, nb);
+  const int z = L / nyb;
+  const int y0 = (L - z * nyb) * R;
+  const int N = nx * ny * nz;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int idx = tid; idx < R * M; idx += nthr) {
+    const int r = idx / M, j = idx - r * M;
+    const int y = y0 + r;
+    T v0[3] = {T(0), T(0), T(0)}, v1[3] = {T(0), T(0), T(0)};
+    if (y < ny) {
+      const size_t row = ((size_t)z * ny + y) * nx;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = 2 * j + h;
+        if (x >= nx) break;
+        const size_t i = row + x;
+        double mi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mi[c] = m[(size_t)c * N + i];
+        if (upd) {
+          double gi[3], mo[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gi[c] = g[(size_t)c * N + i];
+          cayley_step(mi, gi, tau, mo);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            m[(size_t)c * N + i] = mo[c];
+            sbuf[(size_t)c * N + i] = mo[c] - mi[c];
+            mi[c] = mo[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (h == 0) v0[c] = (T)mi[c];
+          else v1[c] = (T)mi[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) buf[(c * R + r) * M + j] = mk(v0[c], v1[c]);
+  }
+  __syncthreads();
+  fft_lds<-1, VPT>(buf, M, 3 * R, M, twx, Px, tid, nthr);
+  const size_t slab = (size_t)3 * nz * ny;
+  const int q3 = 3 * R;
+  for (int idx = tid; idx < (M + 1) * q3; idx += nthr) {
+    const int k = idx / q3, q = idx - k * q3;
+    const int r = q / 3, c = q - r * 3;       // [z][y][c] order: contiguous in q
+    const int y = y0 + r;
+    if (y >= ny) continue;
+    const cx<T>* row = buf + (c * R + r) * M;
+    const cx<T> zk = row[k == M ? 0 : k];
+    const cx<T> zc = conj(row[k == 0 ? 0 : M - k]);
+    const cx<T> w = twx[k];
+    out[(size_t)k * slab + ((size_t)z * ny + y) * 3 + c] =
+        scl(add(add(zk, zc), rot90<-1>(mul(w, sub(zk, zc)))), T(0.5));
+  }
+}
+
+template <typename T, int VPT>
+__global__ void __launch_bounds__(512)
+k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restrict__ Hd_out,
+      MinState* __restrict__ st_fin, double Ms, double V, const cx<T>* __restrict__ twx) {
+  if (a.done != nullptr && *a.done != 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+  __shared__ double scratch[kNPartial * 8];
+  __shared__ int is_last;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int M = Px >> 1;
+  const int nyb = (ny + R - 1) / R;
+  const int nb = nz * nyb;
+  const int L = xcd_remap(blockIdx.x, nb);
+  const int z = L / nyb;
+  const int y0 = (L - z * nyb) * R;
+  const int N = nx * ny * nz;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const size_t slab = (size_t)3 * nz * ny;
+  const int q3 = 3 * R;
+  for (int idx = tid; idx < M * q3; idx += nthr) {
+    const int k = idx / q3, q = idx - k * q3;
+    const int r = q / 3, c = q - r * 3;
+    const int y = y0 + r;
+    cx<T> Zv = mk(T(0), T(0));
+    if (y < ny) {
+      const size_t col = ((size_t)z * ny + y) * 3 + c;
+      const cx<T> Xk = in[(size_t)k * slab + col];
+      const cx<T> Xc = conj(in[(size_t)(M - k) * slab + col]);
+      const cx<T> wi = conj(twx[k]);
+      Zv = scl(add(add(Xk, Xc), rot90<1>(mul(wi, sub(Xk, Xc)))), T(0.5));
+    }
+    buf[(c * R + r) * M + k] = Zv;
+  }
+  __syncthreads();
+  fft_lds<1, VPT>(buf, M, q3, M, twx, Px, tid, nthr);
+  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
+  double part[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int idx = tid; idx < R * nx; idx += nthr) {
+    const int r = idx / nx, x = idx - r * nx;
+    const int y = y0 + r;
+    if (y >= ny) continue;
+    const int i = (z * ny + y) * nx + x;
+    double hd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cx<T> v = buf[(c * R + r) * M + (x >> 1)];
+      hd[c] = (double)((x & 1) ? v.y : v.x);
+    }
+    if (Hd_out != nullptr) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Hd_out[(size_t)c * N + i] = hd[c];
+    }
+    local_cell(a, i, hd, bb, part);
+  }
+  const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
+  block_reduce<kNPartial>(part, is_max, scratch);
+  if (st_fin == nullptr) return;
+  if (tid == 0) {
+#pragma unroll
+    for (int v = 0; v < kNPartial; ++v) a.partials[(size_t)L * kNPartial + v] = part[v];
+    __threadfence();
+    const unsigned prev = atomicAdd(&st_fin->arrive, 1u);
+    is_last = (prev == (unsigned)(nb - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double v[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < nb; b += nthr) {
+#pragma unroll
+    for (int q = 0; q < kNPartial - 1; ++q)
+      v[q] += __hip_atomic_load(&a.partials[(size_t)b * kNPartial + q], __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+    v[7] = fmax(v[7], __hip_atomic_load(&a.partials[(size_t)b * kNPartial + 7], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT));
+  }
+  block_reduce<kNPartial>(v, is_max, scratch);
+  if (tid == 0) {
+    finish_decision(st_fin, v, Ms, V);
+    st_fin->arrive = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-FFT variants (M = Px/2 = 64 VL, VL in {1, 2, 4, 8}).  A block holds R
+// rows; wave w = 3 r + c transforms component c of row r.  Each (row,
+// component) owns an LDS region of wx_region<VL>() elements, used in turn
+// for the natural-order sequence, the transposes of the wave FFT and the
+// spectrum X[0..M]; natural index k is stored at wx_pad(k) = k + k/8 so that
+// the permuted writes of the wave FFT (lanes 8 apart) avoid bank conflicts.
+// Global traffic goes through LDS so that every block moves contiguous
+// chunks of 3 R values per kx.
+// ---------------------------------------------------------------------------
+template <int VL>
+__host__ __device__ constexpr int wx_region() { return VL * 72 + 8; }
+__device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
+
+template <typename T, int VL>
+__global__ void __launch_bounds__(384)
+k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
+       const MinState* __restrict__ st, int nx, int ny, int nz, int R,
+       cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
+  constexpr int M = 64 * VL;
+  constexpr int NG = 8 * VL;
+  constexpr int RG = wx_region<VL>();
+  bool upd = false;
+  double tau = 0.0;
+  if (st != nullptr) {
+    if (st->done != 0) return;
+    upd = st->pending != 0;
+    tau = st->last_tau;
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
+  T* smr = reinterpret_cast<T*>(smem);
+  const int nyb = (ny + R - 1) / R;
+  const int nb = nz * nyb;
+  const int L = xcd_remap(blockIdx.x, nb);
+  const int z = L / nyb;
+  const int y0 = (L - z * nyb) * R;
+  const int rows = min(R, ny - y0);
+  const int N = nx * ny * nz;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  // phase 1: pending update of the rows, sequences into LDS (x = 2j + h -> re/im of j)
+  {
+    constexpr int U = 4;                       // cells in flight per thread
+    const int total = rows * nx;
+    const size_t row0 = ((size_t)z * ny + y0) * nx;   // rows of the block are contiguous
+    for (int base = tid; base < total; base += U * nthr) {
+      double mi[U][3], gi[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nthr;
+        if (idx < total) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            mi[u][c] = m[(size_t)c * N + row0 + idx];
+            gi[u][c] = upd ? g[(size_t)c * N + row0 + idx] : 0.0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nthr;
+        if (idx >= total) continue;
+        const int r = idx / nx, x = idx - r * nx;
+        const size_t i = row0 + idx;
+        if (upd) {
+          double mo[3];
+          cayley_step(mi[u], gi[u], tau, mo);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            m[(size_t)c * N + i] = mo[c];
+            sbuf[(size_t)c * N + i] = mo[c] - mi[u][c];
+            mi[u][c] = mo[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          smr[2 * ((size_t)(r * 3 + c) * RG + (x >> 1)) + (x & 1)] = (T)mi[u][c];
+      }
+    }
+  }
+  // zero padding x in [nx, 2M)
+  const int jz = nx >> 1;   // first complex slot holding padding (its .y if nx is odd)
+  for (int idx = tid; idx < rows * 3 * (M - jz); idx += nthr) {
+    const int q = idx / (M - jz), j = jz + idx - q * (M - jz);
+    if (2 * j >= nx) sm[(size_t)q * RG + j] = mk(T(0), T(0));
+    else smr[2 * ((size_t)q * RG + j) + 1] = T(0);          // x = nx - 1 even: .y is padding
+  }
+  __syncthreads();
+  // phase 2: wave FFT of one (row, component)
+  const int lane = tid & 63, w = tid >> 6;
+  const int r = w / 3, c = w - r * 3;
+  cx<T>* reg = sm + (size_t)w * RG;
+  if (r < rows) {
+    cx<T> v[VL], u[8];
+#pragma unroll
+    for (int q = 0; q < VL; ++q) v[q] = reg[lane + 64 * q];
+    __builtin_amdgcn_wave_barrier();
+    wfft_forward<T, VL, false, 2>(v, u, reg, twx, lane);   // table of length Px = 2M
+    __builtin_amdgcn_wave_barrier();
+    if (lane < NG) {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) reg[wx_pad(wfft_freq<VL>(lane, d))] = u[d];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // split into the spectrum of the real row: X[k] = (Zk + Zc)/2 - i W^k (Zk - Zc)/2
+    cx<T> X[VL + 1];
+#pragma unroll
+    for (int q = 0; q <= VL; ++q) {
+      const int k = lane + 64 * q;
+      const int kk = k < M ? k : 0;
+      const int km = k == 0 ? 0 : (k >= M ? 0 : M - k);
+      const cx<T> zk = reg[wx_pad(kk)];
+      const cx<T> zc = conj(reg[wx_pad(km)]);
+      const cx<T> wk = twx[k < M ? k : M];
+      X[q] = scl(add(add(zk, zc), rot90<-1>(mul(wk, sub(zk, zc)))), T(0.5));
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q <= VL; ++q) {
+      const int k = lane + 64 * q;
+      if (k <= M) reg[wx_pad(k)] = X[q];
+    }
+  }
+  __syncthreads();
+  // phase 3: contiguous chunks of 3 R values per kx
+  const size_t slab = (size_t)3 * nz * ny;
+  const int q3 = 3 * rows;
+  cx<T>* dst = out + ((size_t)z * ny + y0) * 3;
+  for (int idx = tid; idx < (M + 1) * q3; idx += nthr) {
+    const int k = idx / q3, q = idx - k * q3;
+    dst[(size_t)k * slab + q] = sm[(size_t)q * RG + wx_pad(k)];
+  }
+}
+
+template <typename T, int VL>
+__global__ void __launch_bounds__(384)
+k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ Hd_out,
+        MinState* __restrict__ st_fin, double Ms, double V, const cx<T>* __restrict__ twx) {
+  constexpr int M = 64 * VL;
+  constexpr int NG = 8 * VL;
+  constexpr int RG = wx_region<VL>();
+  if (a.done != nullptr && *a.done != 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
+  __shared__ double scratch[kNPartial * 8];
+  __shared__ int is_last;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int nyb = (ny + R - 1) / R;
+  const int nb = nz * nyb;
+  const int L = xcd_remap(blockIdx.x, nb);
+  const int z = L / nyb;
+  const int y0 = (L - z * nyb) * R;
+  const int rows = min(R, ny - y0);
+  const int N = nx * ny * nz;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  // phase 1: spectrum chunks into LDS
+  const size_t slab = (size_t)3 * nz * ny;
+  const int q3 = 3 * rows;
+  const cx<T>* src = in + ((size_t)z * ny + y0) * 3;
+  {
+    constexpr int U = 8;                       // loads in flight per thread
+    const int total = (M + 1) * q3;
+    for (int base = tid; base < total; base += U * nthr) {
+      T re[U], im[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = min(base + u * nthr, total - 1);
+        const int k = idx / q3, q = idx - k * q3;
+        const cx<T> v = src[(size_t)k * slab + q];
+        re[u] = v.x;
+        im[u] = v.y;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nthr;
+        if (idx < total) {
+          const int k = idx / q3, q = idx - k * q3;
+          sm[(size_t)q * RG + wx_pad(k)] = mk(re[u], im[u]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // phase 2: inverse real transform of one (row, component):
+  // Z[k] = (X[k] + conj X[M-k])/2 + i W^-k (X[k] - conj X[M-k])/2, then
+  // z = conj(FFT(conj Z)) and the row samples are x[2j] = Re z[j], x[2j+1] = Im z[j]
+  const int lane = tid & 63, w = tid >> 6;
+  const int r = w / 3, c = w - r * 3;
+  cx<T>* reg = sm + (size_t)w * RG;
+  if (r < rows) {
+    cx<T> v[VL], u[8];
+#pragma unroll
+    for (int q = 0; q < VL; ++q) {
+      const int k = lane + 64 * q;
+      const cx<T> Xk = reg[wx_pad(k)];
+      const cx<T> Xc = conj(reg[wx_pad(M - k)]);
+      const cx<T> wi = conj(twx[k]);
+      v[q] = conj(scl(add(add(Xk, Xc), rot90<1>(mul(wi, sub(Xk, Xc)))), T(0.5)));
+    }
+    __builtin_amdgcn_wave_barrier();
+    wfft_forward<T, VL, false, 2>(v, u, reg, twx, lane);   // table of length Px = 2M
+    __builtin_amdgcn_wave_barrier();
+    if (lane < NG) {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) reg[wx_pad(wfft_freq<VL>(lane, d))] = conj(u[d]);
+    }
+  }
+  __syncthreads();
+  // phase 3: local terms of the rows
+  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
+  double part[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  {
+    constexpr int U = 1;                       // cells per thread per round
+    const int total = rows * nx;
+    const int row0 = (z * ny + y0) * nx;
+    for (int base = tid; base < total; base += U * nthr) {
+      CellIn cin[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nthr;
+        if (idx < total) fetch_cell(a, row0 + idx, bb, cin[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nthr;
+        if (idx >= total) continue;
+        const int rr = idx / nx, x = idx - rr * nx;
+        const int i = row0 + idx;
+        double hd[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          const cx<T> v = sm[(size_t)(rr * 3 + cc) * RG + wx_pad(x >> 1)];
+          hd[cc] = (double)((x & 1) ? v.y : v.x);
+        }
+        if (Hd_out != nullptr) {
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) Hd_out[(size_t)cc * N + i] = hd[cc];
+        }
+        compute_cell(a, i, hd, bb, cin[u], part);
+      }
+    }
+  }
+  const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
+  block_reduce<kNPartial>(part, is_max, scratch);
+  if (st_fin == nullptr) return;
+  if (tid == 0) {
+#pragma unroll
+    for (int v = 0; v < kNPartial; ++v) a.partials[(size_t)L * kNPartial + v] = part[v];
+    __threadfence();
+    const unsigned prev = atomicAdd(&st_fin->arrive, 1u);
+    is_last = (prev == (unsigned)(nb - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double v[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < nb; b += nthr) {
+#pragma unroll
+    for (int q = 0; q < kNPartial - 1; ++q)
+      v[q] += __hip_atomic_load(&a.partials[(size_t)b * kNPartial + q], __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+    v[7] = fmax(v[7], __hip_atomic_load(&a.partials[(size_t)b * kNPartial + 7], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT));
+  }
+  block_reduce<kNPartial>(v, is_max, scratch);
+  if (tid == 0) {
+    finish_decision(st_fin, v, Ms, V);
+    st_fin->arrive = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+static int threads_for(long long values, int vpt) {
+  long long t = (values + vpt - 1) / vpt;
+  t = (t + 63) / 64 * 64;
+  if (t < 64) t = 64;
+  if (t > 512) t = 512;
+  return (int)t;
+}
+
+template <typename K>
+static void set_lds(K kernel, size_t bytes) {
+  if (bytes > 48 * 1024)
+    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+static bool wave_x(int M) { return M == 64 || M == 128 || M == 256 || M == 512; }
+
+int rows_per_block(int M, int ny, bool single) {
+  if (wave_x(M)) return ny >= 2 ? 2 : 1;
+  // 3 R M complex values per block: at most 4096 (VPT 8, 512 threads) and
+  // at most 48 KiB of LDS
+  const int bytes = single ? 8 : 16;
+  int R = 4096 / (3 * M);
+  const int Rl = (48 * 1024) / (3 * M * bytes);
+  if (Rl < R) R = Rl;
+  if (R < 1) R = 1;
+  if (R > ny) R = ny;
+  return R;
+}
+
+template <typename T, int VL>
+static void xf_wave(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st,
+                    int nx, int ny, int nz, int R, void* out, const void* twx) {
+  const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
+  const int nb = nz * ((ny + R - 1) / R);
+  auto k = k_xf_w<T, VL>;
+  set_lds(k, lds);
+  hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, m, g, sbuf, st, nx, ny, nz, R,
+                     (cx<T>*)out, (const cx<T>*)twx);
+}
+
+template <typename T, int VL>
+static void xil_wave(hipStream_t s, const void* in, const LocalArgs& a, int R, double* Hd_out,
+                     MinState* st_fin, double Ms, double V, const void* twx) {
+  const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
+  const int nb = a.nz * ((a.ny + R - 1) / R);
+  auto k = k_xil_w<T, VL>;
+  set_lds(k, lds);
+  hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, (const cx<T>*)in, a, R, Hd_out, st_fin, Ms,
+                     V, (const cx<T>*)twx);
+}
+
+template <typename T>
+void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
+               int ny, int nz, int Px, int R, void* out, const void* twx) {
+  const int M = Px / 2;
+  switch (M) {
+    case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
+    case 128: xf_wave<T, 2>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
+    case 256: xf_wave<T, 4>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
+    case 512: xf_wave<T, 8>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
+    default: break;
+  }
+  const long long vals = 3LL * R * M;
+  const size_t lds = (size_t)vals * sizeof(cx<T>);
+  const int nb = nz * ((ny + R - 1) / R);
+  if (vals <= 4096) {
+    auto k = k_xf<T, 8>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 8)), lds, s, m, g, sbuf, st, nx, ny, nz,
+                       Px, R, (cx<T>*)out, (const cx<T>*)twx);
+  } else {
+    auto k = k_xf<T, 16>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 16)), lds, s, m, g, sbuf, st, nx, ny,
+                       nz, Px, R, (cx<T>*)out, (const cx<T>*)twx);
+  }
+}
+
+template <typename T>
+void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,
+                MinState* st_fin, double Ms, double V, const void* twx) {
+  const int M = Px / 2;
+  switch (M) {
+    case 64: xil_wave<T, 1>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
+    case 128: xil_wave<T, 2>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
+    case 256: xil_wave<T, 4>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
+    case 512: xil_wave<T, 8>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
+    default: break;
+  }
+  const long long vals = 3LL * R * M;
+  const size_t lds = (size_t)vals * sizeof(cx<T>);
+  const int nb = a.nz * ((a.ny + R - 1) / R);
+  if (vals <= 4096) {
+    auto k = k_xil<T, 8>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 8)), lds, s, (const cx<T>*)in, a, Px, R,
+                       Hd_out, st_fin, Ms, V, (const cx<T>*)twx);
+  } else {
+    auto k = k_xil<T, 16>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 16)), lds, s, (const cx<T>*)in, a, Px,
+                       R, Hd_out, st_fin, Ms, V, (const cx<T>*)twx);
+  }
+}
+
+template void launch_xf<double>(hipStream_t, double*, const double*, double*, const MinState*, int,
+                                int, int, int, int, void*, const void*);
+template void launch_xf<float>(hipStream_t, double*, const double*, double*, const MinState*, int,
+                               int, int, int, int, void*, const void*);
+template void launch_xil<double>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
+                                 MinState*, double, double, const void*);
+template void launch_xil<float>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
+                                MinState*, double, double, const void*);
+
+}  // namespace mmk

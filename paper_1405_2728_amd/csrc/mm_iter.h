@@ -1,0 +1,196 @@
+// Per-cell and per-iteration device logic shared by the stand-alone and the
+// fused kernels: local field terms and g (eqs. (5), (8)), the BB sums
+// (eqs. (9), (10), (12)), the stop rule and step choice, and the midpoint
+// update of eq. (7) (descent sign).
+#pragma once
+
+#include "mm_device.h"
+#include "mm_kernels.h"
+
+namespace mmk {
+
+// Inputs of the local terms of one cell, fetched ahead of use so that a
+// thread can keep several cells' loads in flight.  A missing neighbour
+// (free boundary) is replaced by the cell itself, which contributes zero.
+struct CellIn {
+  double m[3];
+  double nb[6][3];   // x-1, x+1, y-1, y+1, z-1, z+1
+  double g[3], s[3];
+  double ku;
+};
+
+__device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, CellIn& d) {
+  const int N = a.nx * a.ny * a.nz;
+  const int x = i % a.nx;
+  const int y = (i / a.nx) % a.ny;
+  const int z = i / (a.nx * a.ny);
+  const int sy = a.nx, sz = a.nx * a.ny;
+  const int j[6] = {x > 0 ? i - 1 : i,        x < a.nx - 1 ? i + 1 : i,
+                    y > 0 ? i - sy : i,       y < a.ny - 1 ? i + sy : i,
+                    z > 0 ? i - sz : i,       z < a.nz - 1 ? i + sz : i};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double* mc = a.m + (size_t)c * N;
+    d.m[c] = mc[i];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) d.nb[q][c] = mc[j[q]];
+  }
+  if (a.g != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d.g[c] = bb ? a.g[(size_t)c * N + i] : 0.0;
+      d.s[c] = bb ? a.s[(size_t)c * N + i] : 0.0;
+    }
+  }
+  d.ku = a.ku_map != nullptr ? a.ku_map[i] : a.ku;
+}
+
+// Local terms of one cell i given its demag field hd: H_eff, g = m x (m x H)
+// (written back when a.g is set) and the eight partial sums
+// [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext, max |g|^2].
+__device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const double hd[3],
+                                             bool bb, const CellIn& d, double part[kNPartial]) {
+  const int N = a.nx * a.ny * a.nz;
+  double hex[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double mc = d.m[c];
+    hex[c] = a.cx * ((d.nb[0][c] - mc) + (d.nb[1][c] - mc)) +
+             a.cy * ((d.nb[2][c] - mc) + (d.nb[3][c] - mc)) +
+             a.cz * ((d.nb[4][c] - mc) + (d.nb[5][c] - mc));
+  }
+  const double* mi = d.m;
+  const double mu = mi[0] * a.u[0] + mi[1] * a.u[1] + mi[2] * a.u[2];
+  const double pan = a.kan * d.ku * mu;
+  double h[3], han[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    han[c] = pan * a.u[c];
+    h[c] = hd[c] + hex[c] + han[c] + a.H[c];
+  }
+  if (a.Hout != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.Hout[(size_t)c * N + i] = h[c];
+  }
+  if (a.Hex_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.Hex_out[(size_t)c * N + i] = hex[c];
+  }
+  if (a.Han_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.Han_out[(size_t)c * N + i] = han[c];
+  }
+  part[3] += mi[0] * hd[0] + mi[1] * hd[1] + mi[2] * hd[2];
+  part[4] += mi[0] * hex[0] + mi[1] * hex[1] + mi[2] * hex[2];
+  part[5] += d.ku * mu * mu;
+  part[6] += mi[0] * a.H[0] + mi[1] * a.H[1] + mi[2] * a.H[2];
+  const double ax = mi[1] * h[2] - mi[2] * h[1];
+  const double ay = mi[2] * h[0] - mi[0] * h[2];
+  const double az = mi[0] * h[1] - mi[1] * h[0];
+  const double g0 = mi[1] * az - mi[2] * ay;
+  const double g1 = mi[2] * ax - mi[0] * az;
+  const double g2 = mi[0] * ay - mi[1] * ax;
+  part[7] = fmax(part[7], g0 * g0 + g1 * g1 + g2 * g2);
+  if (a.g != nullptr) {
+    if (bb) {
+      const double y0 = g0 - d.g[0], y1 = g1 - d.g[1], y2 = g2 - d.g[2];
+      part[0] += d.s[0] * d.s[0] + d.s[1] * d.s[1] + d.s[2] * d.s[2];
+      part[1] += d.s[0] * y0 + d.s[1] * y1 + d.s[2] * y2;
+      part[2] += y0 * y0 + y1 * y1 + y2 * y2;
+    }
+    a.g[i] = g0;
+    a.g[(size_t)N + i] = g1;
+    a.g[2 * (size_t)N + i] = g2;
+  }
+}
+
+__device__ __forceinline__ void local_cell(const LocalArgs& a, int i, const double hd[3],
+                                           bool bb, double part[kNPartial]) {
+  CellIn d;
+  fetch_cell(a, i, bb, d);
+  compute_cell(a, i, hd, bb, d, part);
+}
+
+// Stop rule and step size from the reduced sums v (one thread).  Sets
+// done / tau / k / pending; records torque and energy.
+__device__ __forceinline__ void finish_decision(MinState* st, const double v[kNPartial],
+                                                double Ms, double V) {
+  const double c = -kMu0 * Ms * V;
+  const double Ed = 0.5 * c * v[3], Eex = 0.5 * c * v[4], Ean = -V * v[5], Ez = c * v[6];
+  const double E = Ed + Eex + Ean + Ez;
+  const double T = sqrt(v[7]) / Ms;
+  st->torque = T;
+  st->energy = E;
+  st->eterm[0] = Ed;
+  st->eterm[1] = Eex;
+  st->eterm[2] = Ean;
+  st->eterm[3] = Ez;
+  st->ss = v[0];
+  st->sy = v[1];
+  st->yy = v[2];
+  st->last_k = st->k;
+  st->pending = 0;
+  if (st->mode == 2) return;  // evaluation only
+  st->evals += 1;
+  if (!isfinite(T) || !isfinite(E)) {
+    st->done = -1;
+    return;
+  }
+  const long long k = st->k;
+  if (st->mode == 0) {
+    if (T < st->tol) { st->done = 1; return; }
+    if (k >= st->max_iter) { st->done = 2; return; }
+    if (st->stall_iters > 0) {
+      if (T < st->best_torque) {
+        st->best_torque = T;
+        st->best_k = k;
+      } else if (k - st->best_k >= st->stall_iters) {
+        st->done = 3;
+        return;
+      }
+    }
+  }
+  if (k > 0) {
+    const double ss = v[0], sy = fabs(v[1]), yy = v[2];
+    const double cand = (k & 1) ? ss / sy : sy / yy;
+    if (isfinite(cand) && cand > 0.0) st->tau = cand;
+  }
+  st->last_tau = st->tau;
+  st->k = k + 1;
+  st->pending = 1;
+}
+
+// Midpoint step: m+ = (I - [b]x)^-1 (I + [b]x) m with b = (tau/2) m x H
+// = -(tau/2) m x g for |m| = 1, i.e. m+ = m + 2 (b x m + b x (b x m)) /
+// (1 + |b|^2), followed by renormalisation.
+__device__ __forceinline__ void cayley_step(const double m[3], const double g[3], double tau,
+                                            double out[3]) {
+  const double h = -0.5 * tau;
+  const double b0 = h * (m[1] * g[2] - m[2] * g[1]);
+  const double b1 = h * (m[2] * g[0] - m[0] * g[2]);
+  const double b2 = h * (m[0] * g[1] - m[1] * g[0]);
+  const double c0 = b1 * m[2] - b2 * m[1];
+  const double c1 = b2 * m[0] - b0 * m[2];
+  const double c2 = b0 * m[1] - b1 * m[0];
+  const double d0 = b1 * c2 - b2 * c1;
+  const double d1 = b2 * c0 - b0 * c2;
+  const double d2 = b0 * c1 - b1 * c0;
+  const double f = 2.0 / (1.0 + b0 * b0 + b1 * b1 + b2 * b2);
+  double n0 = m[0] + f * (c0 + d0);
+  double n1 = m[1] + f * (c1 + d1);
+  double n2 = m[2] + f * (c2 + d2);
+  const double inv = 1.0 / sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+  out[0] = n0 * inv;
+  out[1] = n1 * inv;
+  out[2] = n2 * inv;
+}
+
+// Block index -> logical work index so that the blocks a given XCD runs
+// (hardware dispatches block b to XCD b mod 8) cover a contiguous range.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int full = (nb / 8) * 8;
+  if (b >= full) return b;
+  return (b & 7) * (nb / 8) + (b >> 3);
+}
+
+}  // namespace mmk

@@ -29,6 +29,8 @@ struct MinState {
   int mode;            // 0 minimise with stop rule; 1 forced steps; 2 evaluate only
   double last_tau;     // tau used by the most recent update (for step info)
   long long last_k;    // k index of the most recent evaluation
+  int pending;         // 1: an update with last_tau is due before the next evaluation
+  unsigned int arrive; // blocks of the current fused inverse pass that have finished
 };
 
 // Gauss-Legendre rules used by the far-field tensor (nodes on [-1, 1]).
@@ -44,7 +46,7 @@ void launch_newell_octant(hipStream_t s, double* out, int nx, int ny, int nz, do
 void launch_embed_thin(hipStream_t s, const double* oct, double* E, int nx, int ny, int nz, int Px,
                        int Py);
 template <typename T>
-void launch_extract_thin(hipStream_t s, const void* EXY, T* Tt, int M, int nz, int Py);
+void launch_extract_thin(hipStream_t s, const void* EXY, T* Tt, int M, int nz, int Py, int tstride);
 void launch_twiddles(hipStream_t s, void* tw, int P, bool single);
 
 // ---- demag passes ------------------------------------------------------------
@@ -58,8 +60,14 @@ void launch_inv_x(hipStream_t s, const void* in, int rows, int ncomp, int nx_out
 template <typename T>
 void launch_fft_cols(hipStream_t s, void* data, int n, int nseq, const void* tw);
 template <typename T>
-void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt, T scale,
-                    const void* twy, const int* done);
+void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt,
+                    int tstride, T scale, const void* twy, const int* done);
+// elements per kx slab of the thin tensor (padded to 16 bytes)
+inline int thin_tensor_stride(int nz, int Py, bool single) {
+  const int e = nz * (Py / 2 + 1) * 6;
+  const int q = single ? 4 : 2;
+  return (e + q - 1) / q * q;
+}
 bool yz_thin_fits(int nz, int Py, bool single);
 
 // ---- local terms, step size, update -----------------------------------------
@@ -91,6 +99,15 @@ void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int 
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
                         long long stall_iters, int mode);
 void launch_set_mode(hipStream_t s, MinState* st, int mode);
+void launch_clear_pending(hipStream_t s, MinState* st);
+// fused x passes of the thin-film iteration
+int rows_per_block(int M, int ny, bool single);
+template <typename T>
+void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
+               int ny, int nz, int Px, int R, void* out, const void* twx);
+template <typename T>
+void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,
+                MinState* st_fin, double Ms, double V, const void* twx);
 void launch_mean(hipStream_t s, const double* m, int N, double* partials, double* out3);
 
 }  // namespace mmk

@@ -171,7 +171,7 @@ __global__ void k_embed_thin(const double* __restrict__ oct, double* __restrict_
 // part of xz and yz (odd in exactly one transformed axis).
 template <typename T>
 __global__ void k_extract_thin(const cx<double>* __restrict__ EXY, T* __restrict__ Tt, int M,
-                               int nz, int Py) {
+                               int nz, int Py, int tstride) {
   const int nk = Py / 2 + 1;
   const long long total = (long long)(M + 1) * nz * nk * 6;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,7 +183,7 @@ __global__ void k_extract_thin(const cx<double>* __restrict__ EXY, T* __restrict
   const cx<double> v = EXY[(((size_t)kx * 6 + c) * nz + k) * Py + ky];
   // xy and xz are odd in X: their transforms vanish at kx = 0 and kx = M
   const bool zero = (kx == 0 || kx == M) && (c == 3 || c == 4);
-  Tt[idx] = zero ? T(0) : (T)(c < 4 ? v.x : v.y);
+  Tt[(size_t)kx * tstride + (idx - (long long)kx * nz * nk * 6)] = zero ? T(0) : (T)(c < 4 ? v.x : v.y);
 }
 
 void launch_newell_octant(hipStream_t s, double* out, int nx, int ny, int nz, double dx, double dy,
@@ -201,13 +201,13 @@ void launch_embed_thin(hipStream_t s, const double* oct, double* E, int nx, int 
 }
 
 template <typename T>
-void launch_extract_thin(hipStream_t s, const void* EXY, T* Tt, int M, int nz, int Py) {
+void launch_extract_thin(hipStream_t s, const void* EXY, T* Tt, int M, int nz, int Py, int tstride) {
   const long long total = (long long)(M + 1) * nz * (Py / 2 + 1) * 6;
   hipLaunchKernelGGL(k_extract_thin<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     (const cx<double>*)EXY, Tt, M, nz, Py);
+                     (const cx<double>*)EXY, Tt, M, nz, Py, tstride);
 }
 
-template void launch_extract_thin<double>(hipStream_t, const void*, double*, int, int, int);
-template void launch_extract_thin<float>(hipStream_t, const void*, float*, int, int, int);
+template void launch_extract_thin<double>(hipStream_t, const void*, double*, int, int, int, int);
+template void launch_extract_thin<float>(hipStream_t, const void*, float*, int, int, int, int);
 
 }  // namespace mmk

@@ -55,7 +55,7 @@ def test_support_predicate(lib):
 def test_status_strings(lib):
     for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
         assert lib.mm_strerror(code)
-    assert lib.mm_kernel_name(0) == b"fwd_x"
+    assert lib.mm_kernel_name(0) == b"xf"
     assert lib.mm_kernel_name(99) is None
 
 
