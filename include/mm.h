@@ -18,7 +18,10 @@
  *                    keeps the previous tau; first step tau0 = 1e-3/Ms
  *   Sec. 2 (stop)    max_i |g_k^i| / Ms < tol, checked before every update
  *   Sec. 3           demagnetisation field as a zero-padded FFT convolution on
- *                    a regular cuboid grid
+ *                    a regular cuboid grid.  Two paths: grids of at most 4
+ *                    layers transform x and y and convolve directly over the
+ *                    layers (thin-film path); thicker grids transform all
+ *                    three axes (full 3-D path).
  *   Sec. 4           hysteresis loop: one minimiser run per field, started
  *                    from the previous field's magnetisation
  *
@@ -108,8 +111,11 @@ void mm_destroy(mm_ctx* ctx);
 /* Define the regular cuboid grid of one sample (Sec. 3): nx, ny, nz >= 1
  * cells of dx x dy x dz metres.  Computes the demag tensor spectrum on the
  * device (once per geometry) and allocates the sample's work buffers.
- * Resets the minimiser state.  MM_EUNSUPPORTED if the shape exceeds what
- * this build's kernels handle (see mm_supported). */
+ * Resets the minimiser state.  The demag path follows the "demag_path"
+ * option in force at this call.  MM_EUNSUPPORTED if the shape exceeds what
+ * this build's kernels handle (see mm_supported); MM_ENOMEM if the device
+ * cannot hold the set-up temporaries (full 3-D path: about
+ * 192 (Px/2+1) Py Pz bytes, Px, Py, Pz the padded lengths). */
 int mm_set_geometry(mm_ctx* ctx, int sample, int nx, int ny, int nz,
                     double dx, double dy, double dz);
 
@@ -178,14 +184,20 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * between host checks of the stop flag, default 32), "stall_iters" (mixed
  * form: iterations without a new torque minimum before MM_STALLED, default
  * 500; 0 disables), "use_graph" (1 = replay iteration batches as a HIP
- * graph).  Unknown keys give MM_EINVAL. */
+ * graph), "demag_path" (0 = automatic: thin-film path for nz <= 4, full 3-D
+ * path otherwise; 1 = thin-film path only; 2 = full 3-D path also for
+ * nz <= 4; read by mm_set_geometry).  Unknown keys or values give
+ * MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 
 /* Counters of one sample since its last mm_set_geometry: total
  * effective-field evaluations and updates (host int64_t outputs). */
 int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
 
-/* Whether this build's kernels handle a grid (1) or not (0). */
+/* Whether this build's kernels handle a grid (1) or not (0) with the
+ * automatic demag path: nx <= 8192; nz <= 4 with 2ny-1 padded to a power of
+ * two whose 3 nz Py complex values fit one block, or nz > 4 with ny, nz <=
+ * 256 (y and z padded to powers of two in 64..512). */
 int mm_supported(int prec, int nx, int ny, int nz);
 
 /* Per-kernel timing with HIP events on the context's stream.
@@ -194,7 +206,12 @@ int mm_supported(int prec, int nx, int ny, int nz);
  * and clears the totals.  Events add a small gap per timed launch, so time
  * only the kernels of interest.  mm_profile_read(ctx, id, &ms, &launches)
  * reads the accumulated time of kernel id (synchronises).
- * mm_kernel_name(id) names it (NULL past the last id).
+ * mm_kernel_name(id) names it (NULL past the last id): 0 "xf" (pending
+ * update, forward x transform), 1 "yz_thin" (thin-film y transform, tensor
+ * product, inverse), 2 "xil" (inverse x transform, local terms, sums, step
+ * choice), 3 "update" (mm_minimize_step only), 4 "y3_fwd", 5 "z3",
+ * 6 "y3_inv" (full 3-D path: forward y, z transform with tensor product,
+ * inverse y).
  * mm_kernel_bytes(ctx, sample, id, &bytes) gives that kernel's algorithmic
  * bytes per launch in a minimiser iteration (compulsory reads + writes). */
 int mm_profile(mm_ctx* ctx, int mask);

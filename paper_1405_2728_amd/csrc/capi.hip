@@ -15,24 +15,33 @@ using namespace mmk;
 
 namespace {
 
-constexpr int kNumKernels = 4;
-// xf: pending update + forward x FFT; yz_thin: y FFT, tensor product, inverse
-// y FFT; xil: inverse x FFT + local terms + sums + step choice; update:
-// stand-alone update (single-step calls only)
-const char* const kKernelNames[kNumKernels] = {"xf", "yz_thin", "xil", "update"};
-enum { KID_XF = 0, KID_YZ = 1, KID_XIL = 2, KID_UPDATE = 3 };
+constexpr int kNumKernels = 7;
+// xf: pending update + forward x FFT; yz_thin: y FFT, tensor product with the
+// z convolution, inverse y FFT (grids of at most 4 layers); xil: inverse x
+// FFT + local terms + sums + step choice; update: stand-alone update
+// (single-step calls only); y3_fwd, z3, y3_inv: y FFT, z FFT with tensor
+// product and inverse, inverse y FFT (full 3-D path)
+const char* const kKernelNames[kNumKernels] = {"xf",     "yz_thin", "xil",   "update",
+                                               "y3_fwd", "z3",      "y3_inv"};
+enum { KID_XF = 0, KID_YZ = 1, KID_XIL = 2, KID_UPDATE = 3, KID_Y3F = 4, KID_Z3 = 5, KID_Y3I = 6 };
+
+// demag path of a geometry
+enum { PATH_NONE = 0, PATH_THIN = 1, PATH_3D = 2 };
 
 struct Sample {
   bool has_geom = false, has_mat = false;
   int nx = 0, ny = 0, nz = 0, N = 0;
   double dx = 0, dy = 0, dz = 0, V = 0;
-  int Px = 0, Py = 0, M = 0, R3 = 1, nb3 = 0, tstride = 0;
+  int path = PATH_NONE;
+  int Px = 0, Py = 0, Pz = 1, M = 0, R3 = 1, nb3 = 0, tstride = 0;
   double Ms = 0, A = 0, Ku = 0, u[3] = {1, 0, 0}, H[3] = {0, 0, 0};
   double* ku_map = nullptr;
   void* Tt = nullptr;
   void* spec = nullptr;
   void* twx = nullptr;
   void* twy = nullptr;
+  void* twz = nullptr;
+  void* B = nullptr;          // 3-D path: spectrum after the y transform
   double* Hd = nullptr;
   double* g = nullptr;
   double* s = nullptr;
@@ -62,6 +71,7 @@ struct mm_ctx {
   int poll_every = 32;
   long long stall_iters = 500;
   int use_graph = 0;
+  int path_pref = 0;            // 0 automatic, 1 thin-film, 2 full 3-D
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -91,6 +101,27 @@ int next_pow2(int n) {
   return p;
 }
 
+int pad_x(int nx) { return nx < 2 ? 2 : next_pow2(2 * nx - 1); }
+int pad_thin_y(int ny) { return next_pow2(2 * ny - 1); }
+int pad_3d(int n) {
+  const int p = next_pow2(2 * n - 1);
+  return p < 64 ? 64 : p;
+}
+
+// Demag path for a grid: the thin-film path for at most 4 layers (unless the
+// full 3-D path is asked for), the full 3-D path otherwise.
+int choose_path(int prec, int pref, int nx, int ny, int nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return PATH_NONE;
+  if (nx > (1 << 14) || ny > (1 << 13)) return PATH_NONE;
+  if (pad_x(nx) / 2 > 8192) return PATH_NONE;
+  const bool thin_ok = yz_thin_fits(nz, pad_thin_y(ny), prec == MM_MIXED);
+  const bool full_ok = full3d_len_ok(pad_3d(ny)) && full3d_len_ok(pad_3d(nz));
+  if (pref == 1) return thin_ok ? PATH_THIN : PATH_NONE;
+  if (pref == 2) return full_ok ? PATH_3D : PATH_NONE;
+  if (nz <= 4) return thin_ok ? PATH_THIN : PATH_NONE;
+  return full_ok ? PATH_3D : PATH_NONE;
+}
+
 template <typename P>
 void dfree(P*& p) {
   if (p) (void)hipFree((void*)p);
@@ -103,6 +134,8 @@ void free_sample(Sample& s) {
   dfree(s.spec);
   dfree(s.twx);
   dfree(s.twy);
+  dfree(s.twz);
+  dfree(s.B);
   dfree(s.Hd);
   dfree(s.g);
   dfree(s.s);
@@ -253,6 +286,72 @@ int build_tensor(mm_ctx* c, Sample& s) {
   return MM_OK;
 }
 
+// Full 3-D tensor: embed with wrap-around in x, y, z; real x transform;
+// y transform; per (kx, c) plane transpose [z][ky] -> [ky][z]; z transform;
+// keep the real octant ky <= Py/2, kz <= Pz/2.
+int build_tensor3d(mm_ctx* c, Sample& s) {
+  hipStream_t st = c->stream;
+  GaussRules gr;
+  gauss_legendre(6, gr.x6, gr.w6);
+  gauss_legendre(4, gr.x4, gr.w4);
+  gauss_legendre(3, gr.x3, gr.w3);
+  double* oct = nullptr;
+  double* E = nullptr;
+  void* EX = nullptr;
+  void* ET = nullptr;
+  void* tw64[3] = {nullptr, nullptr, nullptr};
+  const size_t n_oct = 6ull * s.N;
+  const size_t n_E = 6ull * s.Pz * s.Py * s.Px;
+  const size_t n_EX = (size_t)(s.M + 1) * 6 * s.Pz * s.Py;
+  auto cleanup = [&]() {
+    dfree(oct);
+    dfree(E);
+    dfree(EX);
+    dfree(ET);
+    for (auto& t : tw64) dfree(t);
+  };
+  if (hipMalloc((void**)&oct, n_oct * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&E, n_E * sizeof(double)) != hipSuccess ||
+      hipMalloc(&EX, n_EX * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&tw64[0], (size_t)s.Px * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&tw64[1], (size_t)s.Py * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&tw64[2], (size_t)s.Pz * 2 * sizeof(double)) != hipSuccess) {
+    cleanup();
+    (void)hipGetLastError();
+    return fail(c, MM_ENOMEM, "device allocation for the tensor set-up failed");
+  }
+  launch_twiddles(st, tw64[0], s.Px, false);
+  launch_twiddles(st, tw64[1], s.Py, false);
+  launch_twiddles(st, tw64[2], s.Pz, false);
+  launch_newell_octant(st, oct, s.nx, s.ny, s.nz, s.dx, s.dy, s.dz, gr);
+  launch_embed_3d(st, oct, E, s.nx, s.ny, s.nz, s.Px, s.Py, s.Pz);
+  const int M = s.M;
+  int R = 8192 / M;
+  if (R > 8) R = 8;
+  if (R < 1) R = 1;
+  launch_fwd_x<double>(st, E, s.Px, s.Px, s.Pz * s.Py, 6, s.Px, R, EX, tw64[0], nullptr);
+  hipError_t e = hipStreamSynchronize(st);
+  dfree(E);                                   // lower the peak before the transpose buffer
+  dfree(oct);
+  if (e == hipSuccess && hipMalloc(&ET, n_EX * 2 * sizeof(double)) != hipSuccess) {
+    cleanup();
+    (void)hipGetLastError();
+    return fail(c, MM_ENOMEM, "device allocation for the tensor set-up failed");
+  }
+  if (e == hipSuccess) {
+    launch_fft_cols<double>(st, EX, s.Py, (M + 1) * 6 * s.Pz, tw64[1]);       // [kx][c][z][ky]
+    launch_transpose_planes(st, EX, ET, s.Pz, s.Py, (M + 1) * 6);           // [kx][c][ky][z]
+    launch_fft_cols<double>(st, ET, s.Pz, (M + 1) * 6 * s.Py, tw64[2]);      // [kx][c][ky][kz]
+    if (single(c)) launch_extract_3d<float>(st, ET, (float*)s.Tt, M, s.Py, s.Pz, s.tstride);
+    else launch_extract_3d<double>(st, ET, (double*)s.Tt, M, s.Py, s.Pz, s.tstride);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  cleanup();
+  if (e != hipSuccess) return fail(c, MM_EHIP, std::string("tensor set-up: ") + hipGetErrorString(e));
+  return MM_OK;
+}
+
 // ---- one effective-field evaluation ----------------------------------------
 struct EvalOut {
   double* Hd = nullptr;       // demag output (NULL: not written)
@@ -305,7 +404,28 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
     else
       launch_xf<double>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, s.R3, s.spec, s.twx);
   }
-  {
+  if (s.path == PATH_3D) {
+    const double scale = -s.Ms / ((double)s.M * (double)s.Py * (double)s.Pz);
+    {
+      Timer t(c, KID_Y3F);
+      if (single(c)) launch_y3<float>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, -1, s.twy, done);
+      else launch_y3<double>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, -1, s.twy, done);
+    }
+    {
+      Timer t(c, KID_Z3);
+      if (single(c))
+        launch_z3<float>(st, s.B, s.nz, s.Py, s.Pz, s.M, (const float*)s.Tt, s.tstride,
+                         (float)scale, s.twz, done);
+      else
+        launch_z3<double>(st, s.B, s.nz, s.Py, s.Pz, s.M, (const double*)s.Tt, s.tstride, scale,
+                          s.twz, done);
+    }
+    {
+      Timer t(c, KID_Y3I);
+      if (single(c)) launch_y3<float>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, 1, s.twy, done);
+      else launch_y3<double>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, 1, s.twy, done);
+    }
+  } else {
     Timer t(c, KID_YZ);
     const double scale = -s.Ms / ((double)s.M * (double)s.Py);
     if (single(c))
@@ -415,12 +535,8 @@ void mm_destroy(mm_ctx* c) {
 }
 
 int mm_supported(int prec, int nx, int ny, int nz) {
-  if (nx < 1 || ny < 1 || nz < 1) return 0;
-  if (nx > (1 << 14) || ny > (1 << 13)) return 0;
-  const int Px = next_pow2(2 * nx - 1) < 2 ? 2 : next_pow2(2 * nx - 1);
-  const int Py = next_pow2(2 * ny - 1);
-  if (Px / 2 > 8192) return 0;
-  return yz_thin_fits(nz, Py, prec == MM_MIXED) ? 1 : 0;
+  if (prec != MM_FP64 && prec != MM_MIXED) return 0;
+  return choose_path(prec, 0, nx, ny, nz) != PATH_NONE ? 1 : 0;
 }
 
 int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, double dy, double dz) {
@@ -430,8 +546,9 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
       !std::isfinite(dy) || !std::isfinite(dz))
     return fail(c, MM_EINVAL, "grid sizes must be >= 1 and cell sizes positive");
   if ((long long)nx * ny * nz > (1LL << 30)) return fail(c, MM_EINVAL, "grid too large");
-  if (!mm_supported(c->prec, nx, ny, nz))
-    return fail(c, MM_EUNSUPPORTED, "grid shape not supported by the thin-film kernels");
+  const int path = choose_path(c->prec, c->path_pref, nx, ny, nz);
+  if (path == PATH_NONE)
+    return fail(c, MM_EUNSUPPORTED, "grid shape not supported by this build's kernels");
   (void)hipStreamSynchronize(c->stream);
   Sample& s = c->smp[sample];
   const double Ms = s.Ms, A = s.A, Ku = s.Ku;
@@ -445,23 +562,28 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.N = nx * ny * nz;
   s.dx = dx; s.dy = dy; s.dz = dz;
   s.V = dx * dy * dz;
-  s.Px = next_pow2(2 * nx - 1);
-  if (s.Px < 2) s.Px = 2;
-  s.Py = next_pow2(2 * ny - 1);
+  s.path = path;
+  s.Px = pad_x(nx);
   s.M = s.Px / 2;
+  const bool full = path == PATH_3D;
+  s.Py = full ? pad_3d(ny) : pad_thin_y(ny);
+  s.Pz = full ? pad_3d(nz) : 1;
   const bool sp = single(c);
   s.R3 = rows_per_block(s.M, ny, sp);
   s.nb3 = nz * ((ny + s.R3 - 1) / s.R3);
   const size_t creal = sp ? sizeof(float) : sizeof(double);
-  s.tstride = thin_tensor_stride(nz, s.Py, sp);
-  const size_t nT = (size_t)(s.M + 1) * s.tstride;
+  s.tstride = full ? tensor3_row(s.Pz, sp) : thin_tensor_stride(nz, s.Py, sp);
+  const size_t nT = (size_t)(s.M + 1) * (full ? (size_t)(s.Py / 2 + 1) : 1) * s.tstride;
   const size_t nspec = (size_t)(s.M + 1) * 3 * nz * ny;
+  const size_t nB = full ? (size_t)(s.M + 1) * s.Py * 3 * nz : 0;
   s.nblk = local_blocks(s.N);
   const size_t npart = (size_t)(s.nblk > s.nb3 ? s.nblk : s.nb3) * kNPartial;
   bool ok = hipMalloc(&s.Tt, nT * creal) == hipSuccess &&
             hipMalloc(&s.spec, nspec * 2 * creal) == hipSuccess &&
             hipMalloc(&s.twx, (size_t)s.Px * 2 * creal) == hipSuccess &&
             hipMalloc(&s.twy, (size_t)s.Py * 2 * creal) == hipSuccess &&
+            (!full || hipMalloc(&s.B, nB * 2 * creal) == hipSuccess) &&
+            (!full || hipMalloc(&s.twz, (size_t)s.Pz * 2 * creal) == hipSuccess) &&
             hipMalloc((void**)&s.Hd, 3ull * s.N * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&s.g, 3ull * s.N * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&s.s, 3ull * s.N * sizeof(double)) == hipSuccess &&
@@ -481,7 +603,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * sizeof(double), c->stream));
   launch_twiddles(c->stream, s.twx, s.Px, sp);
   launch_twiddles(c->stream, s.twy, s.Py, sp);
-  int rc = build_tensor(c, s);
+  if (full) launch_twiddles(c->stream, s.twz, s.Pz, sp);
+  int rc = full ? build_tensor3d(c, s) : build_tensor(c, s);
   if (rc != MM_OK) {
     free_sample(s);
     return rc;
@@ -686,6 +809,9 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->stall_iters = (long long)value;
   } else if (!std::strcmp(key, "use_graph")) {
     c->use_graph = value != 0.0;
+  } else if (!std::strcmp(key, "demag_path")) {
+    if (value != 0 && value != 1 && value != 2) return fail(c, MM_EINVAL, "demag_path is 0, 1 or 2");
+    c->path_pref = (int)value;
   } else {
     return fail(c, MM_EINVAL, std::string("unknown option ") + key);
   }
@@ -733,14 +859,20 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
   const double sr = single(c) ? 4.0 : 8.0;
   const double N3 = 3.0 * s.N * 8.0;                                  // one [3][N] double array
   const double spec = (double)(s.M + 1) * 3 * s.nz * s.ny * 2 * sr;   // spectrum A
-  const double tens = (double)(s.M + 1) * s.tstride * sr;
+  const double trows = s.path == PATH_3D ? (double)(s.Py / 2 + 1) : 1.0;
+  const double tens = (double)(s.M + 1) * trows * s.tstride * sr;
+  const double bsp = s.path == PATH_3D ? (double)(s.M + 1) * s.Py * 3 * s.nz * 2 * sr : 0.0;
   const double ku = s.ku_map ? s.N * 8.0 : 0.0;
+  const bool thin = s.path == PATH_THIN;
   double b = 0;
   switch (id) {
     case KID_XF: b = 4 * N3 + spec; break;          // m, g in; m, s out; spectrum out
-    case KID_YZ: b = 2 * spec + tens; break;        // spectrum in/out; tensor in
+    case KID_YZ: b = thin ? 2 * spec + tens : 0; break;   // spectrum in/out; tensor in
     case KID_XIL: b = spec + 4 * N3 + ku; break;    // spectrum, m, g, s in; g out
     case KID_UPDATE: b = 4 * N3; break;             // m, g in; m, s out
+    case KID_Y3F: b = thin ? 0 : spec + bsp; break; // spectrum in, y spectrum out
+    case KID_Z3: b = thin ? 0 : 2 * bsp + tens; break;    // y spectrum in/out; tensor in
+    case KID_Y3I: b = thin ? 0 : bsp + spec; break;
   }
   *bytes = b;
   return MM_OK;

@@ -48,6 +48,30 @@ void launch_embed_thin(hipStream_t s, const double* oct, double* E, int nx, int 
 template <typename T>
 void launch_extract_thin(hipStream_t s, const void* EXY, T* Tt, int M, int nz, int Py, int tstride);
 void launch_twiddles(hipStream_t s, void* tw, int P, bool single);
+void launch_embed_3d(hipStream_t s, const double* oct, double* E, int nx, int ny, int nz, int Px,
+                     int Py, int Pz);
+void launch_transpose_planes(hipStream_t s, const void* in, void* out, int rows, int cols,
+                             int nplanes);
+template <typename T>
+void launch_extract_3d(hipStream_t s, const void* E, T* T3, int M, int Py, int Pz, int rstride);
+// elements per (kx, ky') row of the 3-D tensor (padded to 16 bytes)
+inline int tensor3_row(int Pz, bool single) {
+  const int e = (Pz / 2 + 1) * 6;
+  const int q = single ? 4 : 2;
+  return (e + q - 1) / q * q;
+}
+// ---- full 3-D path (grids with more than 4 layers) --------------------------
+// y transform of the (kx, z) planes: dir -1: A[kx][z][y][c] -> B[kx][ky][z][c];
+// dir +1: B -> A (rows y < ny kept).
+template <typename T>
+void launch_y3(hipStream_t s, void* A, void* B, int nz, int ny, int Py, int M, int dir,
+               const void* twy, const int* done);
+// z transform of every (kx, ky) pencil of B, product with the tensor, inverse.
+template <typename T>
+void launch_z3(hipStream_t s, void* B, int nz, int Py, int Pz, int M, const T* T3, int rstride,
+               T scale, const void* twz, const int* done);
+// padded y and z lengths handled by the 3-D kernels (powers of two, 64..512)
+inline bool full3d_len_ok(int P) { return P == 64 || P == 128 || P == 256 || P == 512; }
 
 // ---- demag passes ------------------------------------------------------------
 // Rows per block chosen by the host: rows_per_block.

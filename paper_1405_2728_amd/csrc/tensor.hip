@@ -186,6 +186,98 @@ __global__ void k_extract_thin(const cx<double>* __restrict__ EXY, T* __restrict
   Tt[(size_t)kx * tstride + (idx - (long long)kx * nz * nk * 6)] = zero ? T(0) : (T)(c < 4 ? v.x : v.y);
 }
 
+// ---- full 3-D transform of the tensor (grids with more than 4 layers) ------
+// Embed with wrap-around in x, y and z: E[6][Pz][Py][Px].
+__global__ void k_embed_3d(const double* __restrict__ oct, double* __restrict__ E, int nx, int ny,
+                           int nz, int Px, int Py, int Pz) {
+  const long long total = 6LL * Pz * Py * Px;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = (int)(idx % Px);
+  const int jj = (int)((idx / Px) % Py);
+  const int kk = (int)((idx / ((long long)Px * Py)) % Pz);
+  const int c = (int)(idx / ((long long)Px * Py * Pz));
+  int i = -1, j = -1, k = -1;
+  bool nx_ = false, ny_ = false, nz_ = false;
+  if (ii < nx) i = ii;
+  else if (ii > Px - nx) { i = Px - ii; nx_ = true; }
+  if (jj < ny) j = jj;
+  else if (jj > Py - ny) { j = Py - jj; ny_ = true; }
+  if (kk < nz) k = kk;
+  else if (kk > Pz - nz) { k = Pz - kk; nz_ = true; }
+  double v = 0.0;
+  if (i >= 0 && j >= 0 && k >= 0) {
+    v = oct[(size_t)c * nx * ny * nz + ((size_t)k * ny + j) * nx + i];
+    const bool ox = (c == 3 || c == 4), oy = (c == 3 || c == 5), oz = (c == 4 || c == 5);
+    const int flips = (nx_ && ox) + (ny_ && oy) + (nz_ && oz);
+    if (flips & 1) v = -v;
+  }
+  E[idx] = v;
+}
+
+// Per (kx, c) plane: [rows][cols] -> [cols][rows] (complex double), 16 x 16
+// tiles, one block per tile (1-D grid: plane-major).
+__global__ void k_transpose_planes(const cx<double>* __restrict__ in, cx<double>* __restrict__ out,
+                                   int rows, int cols, int tiles_r, int tiles_c) {
+  __shared__ cx<double> tile[16][17];
+  const int tpp = tiles_r * tiles_c;
+  const long long p = blockIdx.x / tpp;
+  const int t = (int)(blockIdx.x - p * tpp);
+  const int r0 = (t / tiles_c) * 16, c0 = (t % tiles_c) * 16;
+  const cx<double>* src = in + (size_t)p * rows * cols;
+  cx<double>* dst = out + (size_t)p * rows * cols;
+  const int tr = threadIdx.y, tc = threadIdx.x;
+  if (r0 + tr < rows && c0 + tc < cols) tile[tr][tc] = src[(size_t)(r0 + tr) * cols + c0 + tc];
+  __syncthreads();
+  if (c0 + tr < cols && r0 + tc < rows) dst[(size_t)(c0 + tr) * rows + r0 + tc] = tile[tc][tr];
+}
+
+// EXYZ[kx][c][ky][kz] -> T3[kx][ky'][kz'][c], ky' <= Py/2, kz' <= Pz/2; rows
+// of the output are padded to rstride elements.  Entries odd in an axis
+// vanish exactly where that axis' frequency is 0 or Nyquist.
+template <typename T>
+__global__ void k_extract_3d(const cx<double>* __restrict__ E, T* __restrict__ T3, int M, int Py,
+                             int Pz, int rstride) {
+  const int nky = Py / 2 + 1, nkz = Pz / 2 + 1;
+  const long long total = (long long)(M + 1) * nky * nkz * 6;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int c = (int)(idx % 6);
+  const int kz = (int)((idx / 6) % nkz);
+  const int ky = (int)((idx / (6LL * nkz)) % nky);
+  const int kx = (int)(idx / (6LL * nkz * nky));
+  const cx<double> v = E[(((size_t)kx * 6 + c) * Py + ky) * Pz + kz];
+  const bool ox = (c == 3 || c == 4), oy = (c == 3 || c == 5), oz = (c == 4 || c == 5);
+  const bool zero = (ox && (kx == 0 || kx == M)) || (oy && (ky == 0 || ky == Py / 2)) ||
+                    (oz && (kz == 0 || kz == Pz / 2));
+  T3[((size_t)kx * nky + ky) * rstride + (size_t)kz * 6 + c] = zero ? T(0) : (T)v.x;
+}
+
+void launch_embed_3d(hipStream_t s, const double* oct, double* E, int nx, int ny, int nz, int Px,
+                     int Py, int Pz) {
+  const long long total = 6LL * Pz * Py * Px;
+  hipLaunchKernelGGL(k_embed_3d, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, oct, E,
+                     nx, ny, nz, Px, Py, Pz);
+}
+
+void launch_transpose_planes(hipStream_t s, const void* in, void* out, int rows, int cols,
+                             int nplanes) {
+  const int tr = (rows + 15) / 16, tc = (cols + 15) / 16;
+  const dim3 grid((unsigned)((long long)nplanes * tr * tc));
+  hipLaunchKernelGGL(k_transpose_planes, grid, dim3(16, 16), 0, s, (const cx<double>*)in,
+                     (cx<double>*)out, rows, cols, tr, tc);
+}
+
+template <typename T>
+void launch_extract_3d(hipStream_t s, const void* E, T* T3, int M, int Py, int Pz, int rstride) {
+  const long long total = (long long)(M + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * 6;
+  hipLaunchKernelGGL(k_extract_3d<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (const cx<double>*)E, T3, M, Py, Pz, rstride);
+}
+
+template void launch_extract_3d<double>(hipStream_t, const void*, double*, int, int, int, int);
+template void launch_extract_3d<float>(hipStream_t, const void*, float*, int, int, int, int);
+
 void launch_newell_octant(hipStream_t s, double* out, int nx, int ny, int nz, double dx, double dy,
                           double dz, const GaussRules& gr) {
   const long long n = (long long)nx * ny * nz;

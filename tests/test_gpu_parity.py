@@ -235,13 +235,144 @@ def test_sp1_size_heff_fp64_and_mixed(torch_cuda):
         ctx.close()
 
 
+# full 3-D path (more than 4 layers, or forced): several tiles of the wave
+# FFTs along y and z, ragged tails, degenerate axes, anisotropic cells
+SHAPES_3D = [
+    ((6, 5, 8), (5e-9, 5e-9, 5e-9)),
+    ((10, 7, 12), (3e-9, 4e-9, 2e-9)),
+    ((17, 3, 33), (2e-9, 2e-9, 3e-9)),
+    ((1, 1, 7), (5e-9, 5e-9, 5e-9)),
+    ((3, 1, 5), (4e-9, 5e-9, 3e-9)),
+    ((1, 40, 6), (5e-9, 5e-9, 5e-9)),
+    ((70, 33, 5), (5e-9, 5e-9, 5e-9)),
+    ((9, 130, 10), (5e-9, 5e-9, 5e-9)),
+]
+
+
+@pytest.mark.parametrize("shape,d", SHAPES_3D)
+def test_heff_terms_fp64_3d(torch_cuda, shape, d):
+    torch = torch_cuda
+    nx, ny, nz = shape
+    say("case heff fp64 3-D", shape, d)
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    ctx, P = make(torch, "fp64", nx, ny, nz, d, Ku=3e4, u=(0.0, 0.6, 0.8), H=(1e4, 2e3, -5e3))
+    m = torch.tensor(m0, device="cuda")
+    Ho = P.heff(m0)
+    e = rel(ctx.heff(0, m).cpu().numpy(), Ho)
+    say("  H_eff rel err", e)
+    assert e < 1e-10
+    hd = ctx.field_terms(0, m)[0].cpu().numpy()
+    assert np.max(np.abs(hd - P.field_terms(m0)["demag"])) < 1e-10 * np.max(np.abs(Ho))
+    E, terms = ctx.energy(0, m)
+    Eo = P.energy_terms(m0)
+    for a, b in zip(terms, Eo):
+        assert abs(a - b) < 1e-10 * sum(abs(x) for x in Eo)
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (7, 5, 3)])
+def test_forced_3d_path_matches_thin_path(torch_cuda, shape):
+    """The two demag paths on the same film: both against the oracle and
+    against each other."""
+    torch = torch_cuda
+    from paper_1405_2728_amd import Context
+    nx, ny, nz = shape
+    d = (5e-9, 4e-9, 3e-9)
+    say("case forced 3-D path", shape)
+    m0 = synth.random_unit(nx, ny, nz, np.random.default_rng(21))
+    Ho = of.Problem(nx, ny, nz, *d, Ms=8e5, A=1.3e-11, Ku=0.0).heff(m0)
+    out = []
+    for path in (1, 2):
+        ctx = Context("fp64")
+        ctx.set_option("demag_path", path)
+        ctx.set_geometry(0, nx, ny, nz, *d)
+        ctx.set_material(0, 8e5, 1.3e-11, 0.0)
+        m = torch.tensor(m0, device="cuda")
+        out.append(ctx.heff(0, m).cpu().numpy())
+        ctx.close()
+    say("  thin", rel(out[0], Ho), "3-D", rel(out[1], Ho), "between", rel(out[1], out[0]))
+    assert rel(out[0], Ho) < 1e-10 and rel(out[1], Ho) < 1e-10
+    assert rel(out[1], out[0]) < 1e-10
+
+
+@pytest.mark.parametrize("shape", [(33, 17, 9), (20, 64, 40)])
+def test_heff_mixed_precision_3d(torch_cuda, shape):
+    torch = torch_cuda
+    nx, ny, nz = shape
+    d = (3e-9,) * 3
+    say("case heff mixed 3-D", shape)
+    m0 = synth.random_unit(nx, ny, nz, np.random.default_rng(8))
+    ctx, P = make(torch, "mixed", nx, ny, nz, d, H=(1e4, 0, 0))
+    m = torch.tensor(m0, device="cuda")
+    e = rel(ctx.heff(0, m).cpu().numpy(), P.heff(m0))
+    say("  mixed H_eff rel err", e)
+    assert e < 1e-5
+    ctx.close()
+
+
+def test_iterates_match_oracle_3d(torch_cuda):
+    torch = torch_cuda
+    nx, ny, nz = 10, 7, 12
+    d = (3e-9,) * 3
+    say("case iterates 3-D", (nx, ny, nz))
+    rng = np.random.default_rng(13)
+    m0 = synth.uniform_with_noise((0.3, 0.2, 1.0), nx, ny, nz, 0.05, rng)
+    ctx, P = make(torch, "fp64", nx, ny, nz, d, Ku=5e4, u=(0, 0, 1), H=(2e4, 0.0, 3e4))
+    m = torch.tensor(m0, device="cuda")
+    ref = om.minimize(P, m0, tol=0.0, max_iter=10, record=True)
+    for k in range(10):
+        info = ctx.minimize_step(0, m)
+        assert info["k"] == k
+        assert abs(info["torque"] - ref["torques"][k]) < 1e-9 * ref["torques"][k]
+        assert abs(info["tau"] / ref["taus"][k] - 1) < 1e-9
+    err = np.max(np.abs(m.cpu().numpy() - ref["m"]))
+    say("  10-iterate max diff", err)
+    assert err < 1e-11
+    ctx.close()
+
+
+def test_cube128_heff_fp64_and_mixed(torch_cuda):
+    """The 128^3 cube of 2 nm cells: full comparison with the oracle's FFT
+    convolution, and the field of the uniform state (mean demag factor 1/3
+    for a cube, by the trace identity and symmetry)."""
+    torch = torch_cuda
+    w = synth.workload(2)
+    nx, ny, nz = w["n"]
+    say("case 128^3 heff")
+    H = w["fields"][3]
+    P = of.Problem(nx, ny, nz, *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"], H_ext=H)
+    Ho = P.heff(w["m0"])
+    uni = np.zeros((3, nz, ny, nx))
+    uni[2] = 1.0
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-5)):
+        ctx, _ = make(torch, prec, nx, ny, nz, w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"],
+                      u=w["u"], H=H)
+        m = torch.tensor(w["m0"], device="cuda")
+        e = rel(ctx.heff(0, m).cpu().numpy(), Ho)
+        say("  ", prec, "rel err", e)
+        assert e < tol
+        hd = ctx.field_terms(0, torch.tensor(uni, device="cuda"))[0].cpu().numpy()
+        nzz = -hd[2].mean() / w["Ms"]
+        say("   mean N_zz of the uniform cube", nzz)
+        assert abs(nzz - 1.0 / 3.0) < (1e-12 if prec == "fp64" else 1e-6)
+        # transverse mean vanishes by symmetry; FP32 convolution leaves ~1e-8 Ms
+        assert np.max(np.abs(hd[:2].mean(axis=(1, 2, 3)))) < (1e-9 if prec == "fp64" else 1e-6) * w["Ms"]
+        ctx.close()
+
+
 def test_error_paths(torch_cuda):
     torch = torch_cuda
     from paper_1405_2728_amd import Context, MMError
     ctx = Context("fp64")
     with pytest.raises(MMError) as ei:
-        ctx.set_geometry(0, 64, 64, 64, 1e-9, 1e-9, 1e-9)
+        ctx.set_geometry(0, 8, 300, 8, 1e-9, 1e-9, 1e-9)      # y padding 1024 in 3-D
     assert ei.value.code == -6
+    ctx.set_option("demag_path", 1)
+    with pytest.raises(MMError) as ei:
+        ctx.set_geometry(0, 8, 8, 8, 1e-9, 1e-9, 1e-9)        # thin path: at most 4 layers
+    assert ei.value.code == -6
+    ctx.set_option("demag_path", 0)
     ctx.set_geometry(0, 8, 4, 1, 5e-9, 5e-9, 5e-9)
     with pytest.raises(MMError) as ei:
         ctx.heff(0, torch.zeros(3 * 32, dtype=torch.float64, device="cuda"))

@@ -50,6 +50,14 @@ def test_support_predicate(lib):
     assert lib.mm_supported(0, 1, 1, 1) == 1
     assert lib.mm_supported(0, 0, 5, 1) == 0
     assert lib.mm_supported(0, 10, 10, 0) == 0
+    # more than 4 layers: full 3-D path, y and z padded to 64..512
+    assert lib.mm_supported(0, 128, 128, 128) == 1
+    assert lib.mm_supported(1, 128, 128, 128) == 1
+    assert lib.mm_supported(0, 1, 1, 5) == 1
+    assert lib.mm_supported(0, 300, 256, 256) == 1
+    assert lib.mm_supported(0, 8, 257, 8) == 0
+    assert lib.mm_supported(0, 8, 8, 257) == 0
+    assert lib.mm_supported(2, 8, 8, 8) == 0
 
 
 def test_status_strings(lib):
@@ -57,6 +65,12 @@ def test_status_strings(lib):
         assert lib.mm_strerror(code)
     assert lib.mm_kernel_name(0) == b"xf"
     assert lib.mm_kernel_name(99) is None
+    names = []
+    k = 0
+    while lib.mm_kernel_name(k) is not None:
+        names.append(lib.mm_kernel_name(k).decode())
+        k += 1
+    assert names == ["xf", "yz_thin", "xil", "update", "y3_fwd", "z3", "y3_inv"]
 
 
 def test_argument_validation_without_gpu(lib):
@@ -78,6 +92,9 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"no_such_key", 1.0) == -1
         assert lib.mm_set_option(h, b"poll_every", 8.0) == 0
         assert lib.mm_set_option(h, b"tau0", -1.0) == -1
+        assert lib.mm_set_option(h, b"demag_path", 3.0) == -1
+        assert lib.mm_set_option(h, b"demag_path", 2.0) == 0
+        assert lib.mm_set_option(h, b"demag_path", 0.0) == 0
     finally:
         lib.mm_destroy(h)
     lib.mm_destroy(None)
