@@ -11,6 +11,9 @@ zero tolerance, so the device-side stop flag and the host polling are
 exercised as in a hysteresis sweep.  Inputs are resident in HBM before the
 clock starts.
 
+With --workload cube the same measurement runs on the 128^3 cube of 2 nm
+cells (full 3-D demag path, random start, 60 mT at 2 degrees from z).
+
 Prints one JSON line.
 """
 
@@ -26,12 +29,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+# name -> (synthetic workload id, field index, description, padded grid)
+WORKLOADS = {
+    "film": (1, 0, "film 400x200x4 cells of 5 nm (Standard Problem 1 stand-in), "
+                   "BB midpoint minimiser, +50 mT at 1 deg", [1024, 512, 4]),
+    "cube": (2, 3, "cube 128^3 cells of 2 nm, full 3-D demag, BB midpoint minimiser, "
+                   "random start, 60 mT at 2 deg from z", [256, 256, 256]),
+}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=400)
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--workload", choices=sorted(WORKLOADS), default="film")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-iters", type=int, default=20)
     p.add_argument("--quick", action="store_true",
@@ -43,7 +56,7 @@ def parse():
     return p.parse_args()
 
 
-def run_gpu(prec, steps, warmup, w, profile):
+def run_gpu(prec, steps, warmup, w, profile, field=0):
     """Warm up, then time `steps` iterations.  With `profile` ("all" or a
     list of kernel names), the library records HIP events around those
     kernels' launches in the timed region (on the library's stream) and the
@@ -54,7 +67,7 @@ def run_gpu(prec, steps, warmup, w, profile):
     ctx = Context(prec)
     ctx.set_geometry(0, nx, ny, nz, *w["d"])
     ctx.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
-    ctx.set_field(0, w["fields"][0])
+    ctx.set_field(0, w["fields"][field])
     m = torch.tensor(w["m0"], dtype=torch.float64, device="cuda")
     ctx.minimize_to_tol(0, m, tol=0.0, max_iter=warmup)
     torch.cuda.synchronize()
@@ -73,10 +86,12 @@ def run_gpu(prec, steps, warmup, w, profile):
             "bytes": kb, "torque": r["torque"]}
 
 
-def stored_traffic(prec, kernel):
+def stored_traffic(prec, kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/traffic_<prec>.json), or None if absent or stale."""
-    p = os.path.join(ROOT, "profiles", "traffic_%s.json" % prec)
+    (profiles/traffic_<prec>.json for the film, traffic_<prec>_<workload>.json
+    otherwise), or None if absent or stale."""
+    suffix = "" if workload == "film" else "_" + workload
+    p = os.path.join(ROOT, "profiles", "traffic_%s%s.json" % (prec, suffix))
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -87,17 +102,18 @@ def stored_traffic(prec, kernel):
     return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(w, iters):
+def cpu_baseline(w, iters, field, label):
     from oracle import fields as of, minimizer as om
     P = of.Problem(*w["n"], *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"],
-                   H_ext=w["fields"][0])
+                   H_ext=w["fields"][field])
     P.heff(w["m0"])                      # tensor and its transform: set-up, not timed
     t0 = time.perf_counter()
     om.minimize(P, w["m0"], tol=0.0, max_iter=iters)
     dt = time.perf_counter() - t0
     return {"value": iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": "%d minimiser iterations of the same 400x200x4 workload "
-                      "(numpy FFT convolution, single thread); tensor set-up excluded" % iters}
+            "sample": "%d minimiser iterations of the same %s workload "
+                      "(numpy FFT convolution, single thread); tensor set-up excluded"
+                      % (iters, label)}
 
 
 def main():
@@ -117,34 +133,36 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 8 * n, "launches": 5}))
         return
-    w = synth.workload(1)
+    wid, field, wdesc, padded = WORKLOADS[a.workload]
+    w = synth.workload(wid)
+    label = "x".join(str(v) for v in w["n"])
     if a.quick:
-        q = run_gpu(a.prec, a.steps, a.warmup, w, profile=False)
+        q = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field)
         print(json.dumps({"value": q["iters"] / q["seconds"], "unit": "iters/s",
                           "precision": a.prec, "steps": a.steps}))
         return
     # timed region (no events)
-    main_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=None)
+    main_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=None, field=field)
     # same region with events around every kernel: the per-kernel breakdown
-    all_run = run_gpu(a.prec, a.steps, a.warmup, w, profile="all")
+    all_run = run_gpu(a.prec, a.steps, a.warmup, w, profile="all", field=field)
     prof = all_run["prof"]
     dom = max(prof, key=lambda k: prof[k][0])
     # same region with events around the dominant kernel only: its duration
-    dom_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=[dom])
+    dom_run = run_gpu(a.prec, a.steps, a.warmup, w, profile=[dom], field=field)
     other = "mixed" if a.prec == "fp64" else "fp64"
-    other_run = run_gpu(other, a.steps, a.warmup, w, profile=None)
-    other_prof = run_gpu(other, a.steps, a.warmup, w, profile="all")["prof"]
+    other_run = run_gpu(other, a.steps, a.warmup, w, profile=None, field=field)
+    other_prof = run_gpu(other, a.steps, a.warmup, w, profile="all", field=field)["prof"]
 
     ips = main_run["iters"] / main_run["seconds"]
     ms, n = dom_run["prof"][dom]
     avg_s = ms / 1e3 / max(n, 1)
     achieved = main_run["bytes"][dom] / avg_s / 1e9
-    traffic = stored_traffic(a.prec, dom)
+    traffic = stored_traffic(a.prec, dom, a.workload)
     per_iter_bytes = sum(main_run["bytes"][k] for k, v in prof.items() if v[1] > 0)
     kernel_us = {k: 1e3 * v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
     oips = other_run["iters"] / other_run["seconds"]
     out = {
-        "metric": "minimiser iterations/s (= H_eff evals/s) at 400x200x4",
+        "metric": "minimiser iterations/s (= H_eff evals/s) at %s" % label,
         "value": ips,
         "unit": "iters/s",
         "n_gpus": 1,
@@ -156,9 +174,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "film 400x200x4 cells of 5 nm (Standard Problem 1 stand-in), "
-                               "BB midpoint minimiser, +50 mT at 1 deg", "precision": a.prec,
-                   "padded_grid": [1024, 512, 4]},
+        "config": {"workload": wdesc, "precision": a.prec, "padded_grid": padded},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0,
                      "unit": "GB/s", "frac": achieved / 8000.0,
                      "traffic": traffic, "avg_kernel_us": avg_s * 1e6,
@@ -173,7 +189,8 @@ def main():
                                             for k, v in other_prof.items() if v[1] > 0}},
     }
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters)
+        iters = a.cpu_iters if a.workload == "film" else max(1, a.cpu_iters // 5)
+        out["cpu_baseline"] = cpu_baseline(w, iters, field, label)
     print(json.dumps(out))
 
 

@@ -211,7 +211,8 @@ int mm_supported(int prec, int nx, int ny, int nz);
  * product, inverse), 2 "xil" (inverse x transform, local terms, sums, step
  * choice), 3 "update" (mm_minimize_step only), 4 "y3_fwd", 5 "z3",
  * 6 "y3_inv" (full 3-D path: forward y, z transform with tensor product,
- * inverse y).
+ * inverse y), 7 "finish" (reduction of the per-block sums, stop rule, step
+ * choice).
  * mm_kernel_bytes(ctx, sample, id, &bytes) gives that kernel's algorithmic
  * bytes per launch in a minimiser iteration (compulsory reads + writes). */
 int mm_profile(mm_ctx* ctx, int mask);

@@ -15,15 +15,17 @@ using namespace mmk;
 
 namespace {
 
-constexpr int kNumKernels = 7;
+constexpr int kNumKernels = 8;
 // xf: pending update + forward x FFT; yz_thin: y FFT, tensor product with the
 // z convolution, inverse y FFT (grids of at most 4 layers); xil: inverse x
 // FFT + local terms + sums + step choice; update: stand-alone update
 // (single-step calls only); y3_fwd, z3, y3_inv: y FFT, z FFT with tensor
-// product and inverse, inverse y FFT (full 3-D path)
+// product and inverse, inverse y FFT (full 3-D path); finish: reduction of
+// the per-block sums, stop rule and step choice
 const char* const kKernelNames[kNumKernels] = {"xf",     "yz_thin", "xil",   "update",
-                                               "y3_fwd", "z3",      "y3_inv"};
-enum { KID_XF = 0, KID_YZ = 1, KID_XIL = 2, KID_UPDATE = 3, KID_Y3F = 4, KID_Z3 = 5, KID_Y3I = 6 };
+                                               "y3_fwd", "z3",      "y3_inv", "finish"};
+enum { KID_XF = 0, KID_YZ = 1, KID_XIL = 2, KID_UPDATE = 3, KID_Y3F = 4, KID_Z3 = 5, KID_Y3I = 6,
+       KID_FINISH = 7 };
 
 // demag path of a geometry
 enum { PATH_NONE = 0, PATH_THIN = 1, PATH_3D = 2 };
@@ -444,12 +446,17 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   a.Han_out = o.Han;
   a.st = mst;
   a.done = done;
+  double* part = o.st_fin ? s.partials : nullptr;
   {
     Timer t(c, KID_XIL);
     if (single(c))
-      launch_xil<float>(st, s.spec, a, s.Px, s.R3, o.Hd, o.st_fin, s.Ms, s.V, s.twx);
+      launch_xil<float>(st, s.spec, a, s.Px, s.R3, o.Hd, part, s.twx);
     else
-      launch_xil<double>(st, s.spec, a, s.Px, s.R3, o.Hd, o.st_fin, s.Ms, s.V, s.twx);
+      launch_xil<double>(st, s.spec, a, s.Px, s.R3, o.Hd, part, s.twx);
+  }
+  if (o.st_fin) {
+    Timer t(c, KID_FINISH);
+    launch_finish(st, s.partials, s.nb3, o.st_fin, s.Ms, s.V);
   }
 }
 
@@ -481,8 +488,13 @@ int read_state(mm_ctx* c, Sample& s) {
 int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
   launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
                      single(c) ? c->stall_iters : 0, 0);
+  // a run evaluates at most max_iter + 1 times: enqueue no iteration beyond
+  // that (such launches would only read the stop flag and return)
+  long long left = (long long)max_iter + 1;
   for (;;) {
-    for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, s, m);
+    const long long batch = left < 1 ? 1 : (left < c->poll_every ? left : c->poll_every);
+    for (long long q = 0; q < batch; ++q) enqueue_iteration(c, s, m);
+    left -= batch;
     HIPCHK(c, hipGetLastError());
     int rc = read_state(c, s);
     if (rc != MM_OK) return rc;
@@ -873,6 +885,7 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
     case KID_Y3F: b = thin ? 0 : spec + bsp; break; // spectrum in, y spectrum out
     case KID_Z3: b = thin ? 0 : 2 * bsp + tens; break;    // y spectrum in/out; tensor in
     case KID_Y3I: b = thin ? 0 : bsp + spec; break;
+    case KID_FINISH: b = (double)s.nb3 * kNPartial * 8.0; break;   // per-block sums
   }
   *bytes = b;
   return MM_OK;

@@ -5,9 +5,12 @@
 //          along x of the updated rows into the spectrum A[kx][z][y][c].
 //   k_xil  inverse x transform of R rows (all three components) -> H_d, then
 //          the local terms, g = m x (m x H) (eq. (8)), the BB sums and the
-//          energy sums of the rows (eq. (12), Sec. 2); the last block to
-//          finish reduces the per-block sums in a fixed order and applies the
-//          stop rule and the alternating step choice.
+//          energy sums of the rows (eq. (12), Sec. 2), one set per block;
+//          a one-block kernel that follows reduces them in a fixed order and
+//          applies the stop rule and the alternating step choice.  (A fused
+//          "last block finishes" variant needs a device-scope release per
+//          block, which writes back the XCD's L2 and cost more than the
+//          extra launch.)
 // Block b works on rows (z, y0 .. y0+R-1) with the XCD-contiguous mapping
 // of xcd_remap so that neighbouring row groups share L2.
 #include "mm_iter.h"
@@ -15,8 +18,11 @@
 
 namespace mmk {
 
+constexpr int kXsThreads = 512;   // launch bound of the LDS-Stockham x passes
+constexpr int kXwThreads = 768;   // launch bound of the wave-FFT x passes (R <= 4)
+
 template <typename T, int VPT>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(kXsThreads)
 k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
      const MinState* __restrict__ st, int nx, int ny, int nz, int Px, int R,
      cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
@@ -92,14 +98,13 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
 }
 
 template <typename T, int VPT>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(kXsThreads)
 k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restrict__ Hd_out,
-      MinState* __restrict__ st_fin, double Ms, double V, const cx<T>* __restrict__ twx) {
+      double* __restrict__ partials, const cx<T>* __restrict__ twx) {
   if (a.done != nullptr && *a.done != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-  __shared__ double scratch[kNPartial * 8];
-  __shared__ int is_last;
+  __shared__ double scratch[kNPartial * kXsThreads / 64];
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int M = Px >> 1;
   const int nyb = (ny + R - 1) / R;
@@ -147,31 +152,10 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
     local_cell(a, i, hd, bb, part);
   }
   const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
-  block_reduce<kNPartial>(part, is_max, scratch);
-  if (st_fin == nullptr) return;
-  if (tid == 0) {
+  block_reduce<kXsThreads>(part, is_max, scratch);
+  if (partials != nullptr && tid == 0) {
 #pragma unroll
-    for (int v = 0; v < kNPartial; ++v) a.partials[(size_t)L * kNPartial + v] = part[v];
-    __threadfence();
-    const unsigned prev = atomicAdd(&st_fin->arrive, 1u);
-    is_last = (prev == (unsigned)(nb - 1)) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double v[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = tid; b < nb; b += nthr) {
-#pragma unroll
-    for (int q = 0; q < kNPartial - 1; ++q)
-      v[q] += __hip_atomic_load(&a.partials[(size_t)b * kNPartial + q], __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-    v[7] = fmax(v[7], __hip_atomic_load(&a.partials[(size_t)b * kNPartial + 7], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT));
-  }
-  block_reduce<kNPartial>(v, is_max, scratch);
-  if (tid == 0) {
-    finish_decision(st_fin, v, Ms, V);
-    st_fin->arrive = 0;
+    for (int v = 0; v < kNPartial; ++v) partials[(size_t)L * kNPartial + v] = part[v];
   }
 }
 
@@ -190,7 +174,7 @@ __host__ __device__ constexpr int wx_region() { return VL * 72 + 8; }
 __device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
 
 template <typename T, int VL>
-__global__ void __launch_bounds__(384)
+__global__ void __launch_bounds__(kXwThreads)
 k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
        const MinState* __restrict__ st, int nx, int ny, int nz, int R,
        cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
@@ -310,17 +294,16 @@ k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict_
 }
 
 template <typename T, int VL>
-__global__ void __launch_bounds__(384)
+__global__ void __launch_bounds__(kXwThreads)
 k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ Hd_out,
-        MinState* __restrict__ st_fin, double Ms, double V, const cx<T>* __restrict__ twx) {
+        double* __restrict__ partials, const cx<T>* __restrict__ twx) {
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
   if (a.done != nullptr && *a.done != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
-  __shared__ double scratch[kNPartial * 8];
-  __shared__ int is_last;
+  __shared__ double scratch[kNPartial * kXwThreads / 64];
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int nyb = (ny + R - 1) / R;
   const int nb = nz * nyb;
@@ -418,31 +401,10 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
     }
   }
   const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
-  block_reduce<kNPartial>(part, is_max, scratch);
-  if (st_fin == nullptr) return;
-  if (tid == 0) {
+  block_reduce<kXwThreads>(part, is_max, scratch);
+  if (partials != nullptr && tid == 0) {
 #pragma unroll
-    for (int v = 0; v < kNPartial; ++v) a.partials[(size_t)L * kNPartial + v] = part[v];
-    __threadfence();
-    const unsigned prev = atomicAdd(&st_fin->arrive, 1u);
-    is_last = (prev == (unsigned)(nb - 1)) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double v[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = tid; b < nb; b += nthr) {
-#pragma unroll
-    for (int q = 0; q < kNPartial - 1; ++q)
-      v[q] += __hip_atomic_load(&a.partials[(size_t)b * kNPartial + q], __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-    v[7] = fmax(v[7], __hip_atomic_load(&a.partials[(size_t)b * kNPartial + 7], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT));
-  }
-  block_reduce<kNPartial>(v, is_max, scratch);
-  if (tid == 0) {
-    finish_decision(st_fin, v, Ms, V);
-    st_fin->arrive = 0;
+    for (int v = 0; v < kNPartial; ++v) partials[(size_t)L * kNPartial + v] = part[v];
   }
 }
 
@@ -465,7 +427,11 @@ static void set_lds(K kernel, size_t bytes) {
 static bool wave_x(int M) { return M == 64 || M == 128 || M == 256 || M == 512; }
 
 int rows_per_block(int M, int ny, bool single) {
-  if (wave_x(M)) return ny >= 2 ? 2 : 1;
+  if (wave_x(M)) {
+    // short rows: 4 per block (12 waves), fewer and larger blocks
+    if (M <= 256 && ny >= 4) return 4;
+    return ny >= 2 ? 2 : 1;
+  }
   // 3 R M complex values per block: at most 4096 (VPT 8, 512 threads) and
   // at most 48 KiB of LDS
   const int bytes = single ? 8 : 16;
@@ -490,13 +456,13 @@ static void xf_wave(hipStream_t s, double* m, const double* g, double* sbuf, con
 
 template <typename T, int VL>
 static void xil_wave(hipStream_t s, const void* in, const LocalArgs& a, int R, double* Hd_out,
-                     MinState* st_fin, double Ms, double V, const void* twx) {
+                     double* partials, const void* twx) {
   const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
   const int nb = a.nz * ((a.ny + R - 1) / R);
   auto k = k_xil_w<T, VL>;
   set_lds(k, lds);
-  hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, (const cx<T>*)in, a, R, Hd_out, st_fin, Ms,
-                     V, (const cx<T>*)twx);
+  hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, (const cx<T>*)in, a, R, Hd_out, partials,
+                     (const cx<T>*)twx);
 }
 
 template <typename T>
@@ -528,13 +494,13 @@ void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const Mi
 
 template <typename T>
 void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,
-                MinState* st_fin, double Ms, double V, const void* twx) {
+                double* partials, const void* twx) {
   const int M = Px / 2;
   switch (M) {
-    case 64: xil_wave<T, 1>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
-    case 128: xil_wave<T, 2>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
-    case 256: xil_wave<T, 4>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
-    case 512: xil_wave<T, 8>(s, in, a, R, Hd_out, st_fin, Ms, V, twx); return;
+    case 64: xil_wave<T, 1>(s, in, a, R, Hd_out, partials, twx); return;
+    case 128: xil_wave<T, 2>(s, in, a, R, Hd_out, partials, twx); return;
+    case 256: xil_wave<T, 4>(s, in, a, R, Hd_out, partials, twx); return;
+    case 512: xil_wave<T, 8>(s, in, a, R, Hd_out, partials, twx); return;
     default: break;
   }
   const long long vals = 3LL * R * M;
@@ -544,12 +510,12 @@ void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R
     auto k = k_xil<T, 8>;
     set_lds(k, lds);
     hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 8)), lds, s, (const cx<T>*)in, a, Px, R,
-                       Hd_out, st_fin, Ms, V, (const cx<T>*)twx);
+                       Hd_out, partials, (const cx<T>*)twx);
   } else {
     auto k = k_xil<T, 16>;
     set_lds(k, lds);
     hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 16)), lds, s, (const cx<T>*)in, a, Px,
-                       R, Hd_out, st_fin, Ms, V, (const cx<T>*)twx);
+                       R, Hd_out, partials, (const cx<T>*)twx);
   }
 }
 
@@ -558,8 +524,8 @@ template void launch_xf<double>(hipStream_t, double*, const double*, double*, co
 template void launch_xf<float>(hipStream_t, double*, const double*, double*, const MinState*, int,
                                int, int, int, int, void*, const void*);
 template void launch_xil<double>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
-                                 MinState*, double, double, const void*);
+                                 double*, const void*);
 template void launch_xil<float>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
-                                MinState*, double, double, const void*);
+                                double*, const void*);
 
 }  // namespace mmk

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
     local_cell(a, i, hd, bb, part);
   }
   const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
-  block_reduce<kNPartial>(part, is_max, scratch);
+  block_reduce<kLocalThreads>(part, is_max, scratch);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int v = 0; v < kNPartial; ++v) a.partials[(size_t)blockIdx.x * kNPartial + v] = part[v];
@@ -41,9 +41,9 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
 
 // Single block: finish the reductions in a fixed order, then (thread 0) the
 // stop rule, the step size of eq. (12) and the iteration counters.
-__global__ void __launch_bounds__(256) k_finish(const double* __restrict__ partials, int nblocks,
-                                                MinState* __restrict__ st, double Ms, double V) {
-  __shared__ double scratch[kNPartial * 4];
+__global__ void __launch_bounds__(1024) k_finish(const double* __restrict__ partials, int nblocks,
+                                                 MinState* __restrict__ st, double Ms, double V) {
+  __shared__ double scratch[kNPartial * 1024 / 64];
   if (st->done != 0) return;
   double v[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_finish(const double* __restrict__ parti
     v[7] = fmax(v[7], partials[(size_t)b * kNPartial + 7]);
   }
   const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
-  block_reduce<kNPartial>(v, is_max, scratch);
+  block_reduce<1024>(v, is_max, scratch);
   if (threadIdx.x != 0) return;
   finish_decision(st, v, Ms, V);
 }
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) k_mean_partial(const double* __restrict__
     v[2] = m[2 * (size_t)N + i];
   }
   const bool is_max[3] = {false, false, false};
-  block_reduce<3>(v, is_max, scratch);
+  block_reduce<256>(v, is_max, scratch);
   if (threadIdx.x == 0)
     for (int c = 0; c < 3; ++c) partials[(size_t)blockIdx.x * 3 + c] = v[c];
 }
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_mean_finish(const double* __restrict__ 
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
     for (int c = 0; c < 3; ++c) v[c] += partials[(size_t)b * 3 + c];
   const bool is_max[3] = {false, false, false};
-  block_reduce<3>(v, is_max, scratch);
+  block_reduce<256>(v, is_max, scratch);
   if (threadIdx.x == 0)
     for (int c = 0; c < 3; ++c) out[c] = v[c] / (double)N;
 }
@@ -130,7 +130,6 @@ __global__ void k_reset_state(MinState* st, double tau0, double tol, long long m
   z.last_tau = tau0;
   z.last_k = 0;
   z.pending = 0;
-  z.arrive = 0;
   *st = z;
 }
 
@@ -163,7 +162,7 @@ void launch_local(hipStream_t s, const LocalArgs& a) {
 
 void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
                    double V) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, st, Ms, V);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partials, nblocks, st, Ms, V);
 }
 
 void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,

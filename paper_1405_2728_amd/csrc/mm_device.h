@@ -194,10 +194,12 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Reduce NV values per thread across the block; result valid in thread 0.
-// scratch: NV * (blockDim/64) doubles of LDS.  is_max[i] selects max vs sum.
-template <int NV>
+// MAXT is the kernel's launch bound (blockDim.x <= MAXT); scratch holds
+// NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs sum.
+template <int MAXT, int NV, int NS>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV],
-                                             double* scratch) {
+                                             double (&scratch)[NS]) {
+  static_assert(NS >= NV * (MAXT / 64), "reduction scratch smaller than one slot per wave");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;

@@ -30,7 +30,6 @@ struct MinState {
   double last_tau;     // tau used by the most recent update (for step info)
   long long last_k;    // k index of the most recent evaluation
   int pending;         // 1: an update with last_tau is due before the next evaluation
-  unsigned int arrive; // blocks of the current fused inverse pass that have finished
 };
 
 // Gauss-Legendre rules used by the far-field tensor (nodes on [-1, 1]).
@@ -130,8 +129,9 @@ template <typename T>
 void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
                int ny, int nz, int Px, int R, void* out, const void* twx);
 template <typename T>
+// partials: per-block sums out (NULL: none), reduced by launch_finish
 void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,
-                MinState* st_fin, double Ms, double V, const void* twx);
+                double* partials, const void* twx);
 void launch_mean(hipStream_t s, const double* m, int N, double* partials, double* out3);
 
 }  // namespace mmk

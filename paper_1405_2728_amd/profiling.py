@@ -93,7 +93,8 @@ def cmd_traffic(a):
         kernels[k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb}
     # bench.py looks kernels up by the library's timing names
     alias = {"k_xf_w": "xf", "k_xf": "xf", "k_yz_wave": "yz_thin", "k_yz_thin": "yz_thin",
-             "k_xil_w": "xil", "k_xil": "xil", "k_update": "update"}
+             "k_xil_w": "xil", "k_xil": "xil", "k_update": "update", "k_y3_fwd": "y3_fwd",
+             "k_z3": "z3", "k_y3_inv": "y3_inv"}
     for k in list(kernels):
         base = k.split("<")[0]
         if base in alias:

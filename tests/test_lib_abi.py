@@ -70,7 +70,7 @@ def test_status_strings(lib):
     while lib.mm_kernel_name(k) is not None:
         names.append(lib.mm_kernel_name(k).decode())
         k += 1
-    assert names == ["xf", "yz_thin", "xil", "update", "y3_fwd", "z3", "y3_inv"]
+    assert names == ["xf", "yz_thin", "xil", "update", "y3_fwd", "z3", "y3_inv", "finish"]
 
 
 def test_argument_validation_without_gpu(lib):
