@@ -19,6 +19,11 @@ Finite-Difference Micromagnetics" (arXiv:1405.2728):
                    the Barzilai-Borwein step sizes of eq. (12) used alternately,
                    the torque stop rule and the warm-started hysteresis sweep of
                    Sec. 4.
+* ``adjoint``   -- derivatives of U (for automatic differentiation), the
+                   Riemannian Hessian on the product of unit spheres, conjugate
+                   gradients for the adjoint field of a relaxed state and the
+                   implicit parameter gradients (calculus on the energy of Sec. 2;
+                   not in the paper).
 
 Every function states the passage it follows.  Readings of passages that are
 garbled or silent in the paper are listed in each module's docstring.

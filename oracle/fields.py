@@ -73,7 +73,8 @@ class Problem:
         return self._N
 
     def _dense(self):
-        """Dense [3N, 3N] matrix of the direct sum, built from the tensor."""
+        """Dense [3N, 3N] matrix of sum_j N(r_i - r_j) . m_j, built from the
+        tensor (Ms is applied at evaluation, so it may change afterwards)."""
         if self._D is None:
             nx, ny, nz = self.n
             k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
@@ -86,14 +87,14 @@ class Problem:
             D = np.zeros((3, ncell, 3, ncell))
             for a in range(3):
                 for b in range(3):
-                    D[a, :, b, :] = -self.Ms * M[a, b][ok, oj, oi]
+                    D[a, :, b, :] = M[a, b][ok, oj, oi]
             self._D = D.reshape(3 * ncell, 3 * ncell)
         return self._D
 
     def h_demag_direct(self, m):
         """H_d,i = -Ms sum_j N(r_i - r_j) m_j by the plain O(N^2) sum."""
         shape = m.shape
-        return (self._dense() @ m.reshape(-1)).reshape(shape)
+        return -self.Ms * (self._dense() @ m.reshape(-1)).reshape(shape)
 
     def h_demag_fft(self, m):
         """The same convolution, zero-padded to 2n per axis (1 if n = 1) and
