@@ -24,12 +24,18 @@ is in the paper.
   For the retraction R(t) = normalise(m + t v) the second derivative of
   U(R(t)) at t = 0 is exactly <v, Hess v> (at any m, not only at a
   stationary point), which is what the tests pin it against.
+  Along the normal direction m_i itself the same expression has curvature
+  m_i . H_eff,i, which is negative where the self-demag field dominates;
+  the operator is therefore applied to P v (identity for tangent v) and the
+  CG directions are projected every step, so that rounding components along
+  m cannot be amplified by the Krylov iteration.
 * Implicit (adjoint) gradient of an objective J(m*) of a relaxed state m*
   (P dU/dm = 0): with Hess lam = P dJ/dm (solved by conjugate gradients on
   the tangent space), dJ/dtheta = -lam . d(dU/dm)/dtheta, i.e.
     dJ/dKu_i = 2 V (m_i . u)(lam_i . u)
     dJ/dA    = mu0 Ms V sum_i lam_i . H_ex,i(A = 1)
     dJ/dMs   = mu0 V sum_i lam_i . (2 H_d,i + H_ext)
+    dJ/dH    = mu0 Ms V sum_i lam_i
 """
 
 import copy
@@ -67,9 +73,10 @@ def h_linear(P, v):
 
 
 def hessvec(P, m, v, H_m=None):
-    """Riemannian Hessian of U at m applied to the tangent field v."""
+    """Riemannian Hessian of U at m applied to P v (v tangent: v itself)."""
     if H_m is None:
         H_m = P.heff(m)
+    v = project(m, v)
     mH = np.sum(m * H_m, axis=0, keepdims=True)
     return MU0 * P.Ms * P.V * (-project(m, h_linear(P, v)) + mH * v)
 
@@ -93,14 +100,14 @@ def cg_solve(P, m, rhs, tol=1e-10, max_iter=10000):
         x += alpha * p
         r -= alpha * Ap
         rr_new = float(np.sum(r * r))
-        p = r + (rr_new / rr) * p
+        p = project(m, r + (rr_new / rr) * p)
         rr = rr_new
         it += 1
     return x, it, float(np.sqrt(rr / bb))
 
 
 def param_grads(P, m, lam):
-    """dJ/dA, dJ/dMs and dJ/dKu_i from the adjoint field lam at m."""
+    """dJ/dA, dJ/dMs, dJ/dKu_i and dJ/dH_ext from the adjoint field lam at m."""
     Q = copy.copy(P)
     Q.A = 1.0
     hex1 = Q.h_exchange(m)
@@ -110,4 +117,5 @@ def param_grads(P, m, lam):
     lu = np.einsum("c...,c->...", lam, P.u)
     return {"A": MU0 * P.Ms * P.V * float(np.sum(lam * hex1)),
             "Ms": MU0 * P.V * float(np.sum(lam * (2.0 * hd + hz))),
-            "Ku": 2.0 * P.V * mu * lu}
+            "Ku": 2.0 * P.V * mu * lu,
+            "H_ext": MU0 * P.Ms * P.V * lam.reshape(3, -1).sum(axis=1)}

@@ -91,7 +91,37 @@ def relaxed(P, m0, tol=1e-11):
     return r["m"]
 
 
-@pytest.mark.parametrize("param,rel_eps", [("Ku", 3e-2), ("A", 3e-3), ("Ms", 1e-3)])
+def test_cg_converges_where_self_demag_dominates():
+    """24x12x1 film after a 0..-5 mT sweep: m . H_eff < 0 in most cells (the
+    self-demag field), so the curvature along m is negative; CG on the
+    tangent space must still converge, and the gradient must match
+    re-relaxation."""
+    n = (24, 12, 1)
+    rng = np.random.default_rng(1)
+    ku = 500 * (1 + 0.1 * rng.standard_normal(n[::-1]))
+    P = of.Problem(*n, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=ku, u=(1, 0, 0))
+    m0 = synth.uniform_with_noise((1, 0, 0), *n, 1e-3, rng)
+    fields = -np.arange(0, 6, 1.0)[:, None] * synth.MT * synth.tilted(1.0)[None, :]
+    m = om.sweep(P, m0, fields, tol=1e-11)["m"]
+    P.H_ext = fields[-1]
+    assert np.mean(np.sum(m * P.heff(m), axis=0) < 0) > 0.5
+    dJ = np.zeros_like(m)
+    dJ[0] = 1.0 / m[0].size
+    lam, it, res = oa.cg_solve(P, m, dJ, tol=1e-11, max_iter=2000)
+    assert res < 1e-11, (it, res)
+    g = oa.param_grads(P, m, lam)
+
+    def J(A):
+        Q = copy.deepcopy(P)
+        Q.A = A
+        return float(relaxed(Q, m, tol=1e-12)[0].mean())
+
+    eps = 3e-3 * P.A
+    fd = (J(P.A + eps) - J(P.A - eps)) / (2 * eps)
+    assert abs(fd - g["A"]) < 1e-4 * abs(g["A"]), (fd, g["A"])
+
+
+@pytest.mark.parametrize("param,rel_eps", [("Ku", 3e-2), ("A", 3e-3), ("Ms", 1e-3), ("Hy", 3e-2)])
 def test_adjoint_gradient_matches_re_relaxation(param, rel_eps):
     """J = mean m_x of the relaxed state; dJ/dtheta from the adjoint against
     central differences of states re-relaxed to torque 1e-12.  Error budget:
@@ -115,12 +145,17 @@ def test_adjoint_gradient_matches_re_relaxation(param, rel_eps):
         if param == "Ku":
             Q.Ku = P.Ku.copy()
             Q.Ku[0, 1, 2] += s
+        elif param == "Hy":
+            Q.H_ext = P.H_ext.copy()
+            Q.H_ext[1] += s
         else:
             setattr(Q, param, getattr(P, param) + s)
         return J(relaxed(Q, m, tol=1e-12))
 
     if param == "Ku":
         eps, ref = rel_eps * float(P.Ku[0, 1, 2]), g["Ku"][0, 1, 2]
+    elif param == "Hy":
+        eps, ref = rel_eps * float(np.linalg.norm(P.H_ext)), g["H_ext"][1]
     else:
         eps, ref = rel_eps * getattr(P, param), g[param]
     fd = (perturbed(eps) - perturbed(-eps)) / (2 * eps)
