@@ -177,6 +177,51 @@ int mm_minimize_to_tol(mm_ctx* ctx, int sample, double* m, double tol,
 int mm_hysteresis_sweep(mm_ctx* ctx, double* const* m, const double* H, int n_fields,
                         double tol, int64_t max_iter, double* m_avg, int64_t* iters);
 
+/* ---- derivatives (calculus on the energy U of Sec. 2; not in the paper) ----
+ * dU/dm_i = -mu0 Ms V H_eff,i (eq. (5)); the constraint |m_i| = 1 makes the
+ * relevant second derivative the Riemannian Hessian on the product of unit
+ * spheres, Hess v = mu0 Ms V [ -P(H_lin[v]) + (m . H_eff(m)) v ] with
+ * P_i = I - m_i m_i^T and H_lin the demag + exchange + anisotropy field of v
+ * (no Zeeman term).  At a relaxed state m* (P dU/dm = 0) an objective J(m*)
+ * has the implicit gradient dJ/dtheta = -lam . d(dU/dm)/dtheta with
+ * Hess lam = P dJ/dm (the adjoint field). */
+
+/* out = Hess(m) P v (for a tangent field v, v_i . m_i = 0, simply Hess v);
+ * m, v, out device [3][N] double (out may alias v, not m).  The result is
+ * tangent.  The normal direction is projected out first: along m_i the
+ * expression has curvature m_i . H_eff,i, which is negative where the
+ * self-demag field dominates. */
+int mm_hessvec(mm_ctx* ctx, int sample, const double* m, const double* v, double* out);
+
+/* Adjoint field: solve Hess(m) lam = P rhs by conjugate gradients on the
+ * tangent space, starting from lam = 0, until |r| <= tol |P rhs| or max_iter
+ * iterations.  m, rhs (dJ/dm), lam: device [3][N] double; lam is written.
+ * iters, resid (host, may be NULL): iterations and final |r|/|P rhs|.
+ * Every search direction is projected onto the tangent space.  Returns
+ * MM_OK, MM_NOT_CONVERGED, or MM_ENONFINITE when a search direction has
+ * non-positive curvature (m is not a strict local minimum) or a value is not
+ * finite.  Synchronises. */
+int mm_adjoint_solve(mm_ctx* ctx, int sample, const double* m, const double* rhs, double* lam,
+                     double tol, int64_t max_iter, int64_t* iters, double* resid);
+
+/* Implicit parameter gradients from the adjoint field lam at m:
+ *   dJ/dA    = mu0 Ms V sum_i lam_i . H_ex,i(A = 1)       (host *dJ_dA)
+ *   dJ/dMs   = mu0 V sum_i lam_i . (2 H_d,i + H_ext)      (host *dJ_dMs)
+ *   dJ/dH    = mu0 Ms V sum_i lam_i                        (host double[3])
+ *   dJ/dKu_i = 2 V (m_i . u)(lam_i . u)                   (device [N])
+ * Outputs may be NULL.  Synchronises. */
+int mm_param_grads(mm_ctx* ctx, int sample, const double* m, const double* lam, double* dJ_dA,
+                   double* dJ_dMs, double* dJ_dH, double* dJ_dKu);
+
+/* Derivatives of U(m; Ms, A, Ku, H_ext) at m:
+ *   dU_dm  (device [3][N] or NULL) = -mu0 Ms V H_eff
+ *   dU_dKu (device [N] or NULL)    = -V (m_i . u)^2
+ *   scal5  (host double[5] or NULL) = { dU/dMs = (2 U_demag + U_zeeman)/Ms,
+ *            dU/dA = U_exchange at A = 1, dU/dH_ext (3) = -mu0 Ms V sum_i m_i }.
+ * Synchronises. */
+int mm_energy_grads(mm_ctx* ctx, int sample, const double* m, double* dU_dm, double* dU_dKu,
+                    double* scal5);
+
 /* Mean magnetisation of m (device [3][N]) into host double[3]. */
 int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
 

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["capi.hip", "demag.hip", "demag3d.hip", "tensor.hip", "local.hip", "iter.hip"]
+SOURCES = ["capi.hip", "demag.hip", "demag3d.hip", "tensor.hip", "local.hip", "iter.hip", "adjoint.hip"]
 LIB_NAME = "libmmbb.so"
 
 FLAGS = [

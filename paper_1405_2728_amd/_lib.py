@@ -44,6 +44,15 @@ SIGNATURES = {
                                       C.c_int, C.c_double, C.c_int64, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]),
     "mm_mean": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
+    "mm_hessvec": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_adjoint_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_int64, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]),
+    "mm_param_grads": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_void_p]),
+    "mm_energy_grads": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(C.c_double)]),
     "mm_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
     "mm_counters": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mm_supported": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),

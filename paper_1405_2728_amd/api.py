@@ -181,6 +181,59 @@ class Context:
             iters.ctypes.data_as(C.POINTER(C.c_int64))), allow_positive=True)
         return mavg, iters, rc
 
+    # -- derivatives ------------------------------------------------------------
+    def hessvec(self, sample, m, v, out=None):
+        """Riemannian Hessian of U at m applied to the tangent field v."""
+        n = self._n3(sample)
+        if out is None:
+            out = self._new_field(sample)
+        self._check(self._lib.mm_hessvec(self._h, sample, _dev_ptr(m, n, "m"), _dev_ptr(v, n, "v"),
+                                         _dev_ptr(out, n, "out")))
+        return out
+
+    def adjoint_solve(self, sample, m, rhs, tol=1e-10, max_iter=10000, out=None):
+        """Adjoint field lam with Hess(m) lam = P rhs (conjugate gradients).
+        Returns (lam, iterations, relative residual, status)."""
+        n = self._n3(sample)
+        if out is None:
+            out = self._new_field(sample)
+        it = C.c_int64()
+        res = C.c_double()
+        rc = self._check(self._lib.mm_adjoint_solve(
+            self._h, sample, _dev_ptr(m, n, "m"), _dev_ptr(rhs, n, "rhs"), _dev_ptr(out, n, "lam"),
+            float(tol), int(max_iter), C.byref(it), C.byref(res)), allow_positive=True)
+        return out, it.value, res.value, rc
+
+    def param_grads(self, sample, m, lam, ku=True):
+        """Implicit gradients: dict with "A", "Ms" (floats), "H_ext" (3
+        floats) and "Ku" (map [nz, ny, nx] or None)."""
+        import torch
+        n = self._n3(sample)
+        dA = C.c_double()
+        dMs = C.c_double()
+        dH = (C.c_double * 3)()
+        dKu = None
+        if ku:
+            nx, ny, nz = self._shape[sample]
+            dKu = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+        self._check(self._lib.mm_param_grads(
+            self._h, sample, _dev_ptr(m, n, "m"), _dev_ptr(lam, n, "lam"), C.byref(dA),
+            C.byref(dMs), dH, _dev_ptr(dKu, n // 3, "dKu") if ku else None))
+        return {"A": dA.value, "Ms": dMs.value, "H_ext": np.array(dH[:]), "Ku": dKu}
+
+    def energy_grads(self, sample, m):
+        """Derivatives of U at m: dict with "m" (tensor), "Ku" (tensor), "Ms",
+        "A" (floats) and "H_ext" (3 floats)."""
+        import torch
+        n = self._n3(sample)
+        nx, ny, nz = self._shape[sample]
+        dm = self._new_field(sample)
+        dku = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+        sc = (C.c_double * 5)()
+        self._check(self._lib.mm_energy_grads(self._h, sample, _dev_ptr(m, n, "m"),
+                                              _dev_ptr(dm, n), _dev_ptr(dku, n // 3), sc))
+        return {"m": dm, "Ku": dku, "Ms": sc[0], "A": sc[1], "H_ext": np.array(sc[2:5])}
+
     def counters(self, sample):
         e = C.c_int64()
         i = C.c_int64()

@@ -54,6 +54,16 @@ struct Sample {
   MinState* st_host = nullptr;
   double* dev3 = nullptr;
   double* host3 = nullptr;
+  // derivative workspace (allocated on first use): H_eff(m), H_lin[v], CG vectors
+  double* Hm = nullptr;
+  double* Hlin = nullptr;
+  double* cr = nullptr;
+  double* cp = nullptr;
+  double* cAp = nullptr;
+  CGState* cg = nullptr;
+  CGState* cg_host = nullptr;
+  double* scal = nullptr;
+  double* scal_host = nullptr;
   int64_t evals_total = 0, iters_total = 0;
 };
 
@@ -145,6 +155,17 @@ void free_sample(Sample& s) {
   dfree(s.st);
   dfree(s.st_eval);
   dfree(s.dev3);
+  dfree(s.Hm);
+  dfree(s.Hlin);
+  dfree(s.cr);
+  dfree(s.cp);
+  dfree(s.cAp);
+  dfree(s.cg);
+  dfree(s.scal);
+  if (s.cg_host) (void)hipHostFree(s.cg_host);
+  if (s.scal_host) (void)hipHostFree(s.scal_host);
+  s.cg_host = nullptr;
+  s.scal_host = nullptr;
   if (s.st_host) (void)hipHostFree(s.st_host);
   if (s.host3) (void)hipHostFree(s.host3);
   s.st_host = nullptr;
@@ -362,9 +383,12 @@ struct EvalOut {
   double* Han = nullptr;
   bool iterate = false;       // minimiser iteration: pending update, g, BB sums
   MinState* st_fin = nullptr; // state the sums are reduced into (NULL: none)
+  bool zeeman = true;         // false: linear part of H_eff only (no H_ext)
+  bool unit_A = false;        // exchange with A = 1 (derivative of H_ex by A)
+  const int* done = nullptr;  // flag that skips the demag and local passes
 };
 
-LocalArgs local_args(const Sample& s) {
+LocalArgs local_args(const Sample& s, bool unit_A = false, bool zeeman = true) {
   LocalArgs a;
   a.m = nullptr;
   a.Hd = nullptr;
@@ -377,7 +401,7 @@ LocalArgs local_args(const Sample& s) {
   a.nx = s.nx;
   a.ny = s.ny;
   a.nz = s.nz;
-  const double pre = 2.0 * s.A / (kMu0Host * s.Ms);
+  const double pre = 2.0 * (unit_A ? 1.0 : s.A) / (kMu0Host * s.Ms);
   a.cx = pre / (s.dx * s.dx);
   a.cy = pre / (s.dy * s.dy);
   a.cz = pre / (s.dz * s.dz);
@@ -385,9 +409,10 @@ LocalArgs local_args(const Sample& s) {
   a.kan = 2.0 / (kMu0Host * s.Ms);
   for (int q = 0; q < 3; ++q) {
     a.u[q] = s.u[q];
-    a.H[q] = s.H[q];
+    a.H[q] = zeeman ? s.H[q] : 0.0;
   }
   a.partials = s.partials;
+  a.Hdyn = nullptr;
   a.st = nullptr;
   a.done = nullptr;
   return a;
@@ -397,7 +422,7 @@ LocalArgs local_args(const Sample& s) {
 void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   hipStream_t st = c->stream;
   MinState* mst = o.iterate ? s.st : nullptr;
-  const int* done = mst ? &mst->done : nullptr;
+  const int* done = mst ? &mst->done : o.done;
   double* mm = const_cast<double*>(m);
   {
     Timer t(c, KID_XF);
@@ -437,7 +462,7 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
       launch_yz_thin<double>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const double*)s.Tt, s.tstride,
                              scale, s.twy, done);
   }
-  LocalArgs a = local_args(s);
+  LocalArgs a = local_args(s, o.unit_A, o.zeeman);
   a.m = m;
   a.g = o.iterate ? s.g : nullptr;
   a.s = o.iterate ? s.s : nullptr;
@@ -446,6 +471,7 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   a.Han_out = o.Han;
   a.st = mst;
   a.done = done;
+  a.Hdyn = mst ? mst->H : nullptr;   // the minimiser's field lives in its state
   double* part = o.st_fin ? s.partials : nullptr;
   {
     Timer t(c, KID_XIL);
@@ -487,7 +513,7 @@ int read_state(mm_ctx* c, Sample& s) {
 
 int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
   launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                     single(c) ? c->stall_iters : 0, 0);
+                     single(c) ? c->stall_iters : 0, 0, s.H);
   // a run evaluates at most max_iter + 1 times: enqueue no iteration beyond
   // that (such launches would only read the stop flag and return)
   long long left = (long long)max_iter + 1;
@@ -513,6 +539,57 @@ int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm
   }
   if (h.done == -1) return fail(c, MM_ENONFINITE, "non-finite torque or energy");
   return status_of(h.done);
+}
+
+// Allocate the derivative workspace of a sample on first use.
+int ensure_adj(mm_ctx* c, Sample& s) {
+  if (s.Hm) return MM_OK;
+  const size_t b3 = 3ull * s.N * sizeof(double);
+  bool ok = hipMalloc((void**)&s.Hm, b3) == hipSuccess && hipMalloc((void**)&s.Hlin, b3) == hipSuccess &&
+            hipMalloc((void**)&s.cr, b3) == hipSuccess && hipMalloc((void**)&s.cp, b3) == hipSuccess &&
+            hipMalloc((void**)&s.cAp, b3) == hipSuccess &&
+            hipMalloc((void**)&s.cg, sizeof(CGState)) == hipSuccess &&
+            hipMalloc((void**)&s.scal, 8 * sizeof(double)) == hipSuccess &&
+            hipHostMalloc((void**)&s.cg_host, sizeof(CGState), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&s.scal_host, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    dfree(s.Hm);
+    dfree(s.Hlin);
+    dfree(s.cr);
+    dfree(s.cp);
+    dfree(s.cAp);
+    dfree(s.cg);
+    dfree(s.scal);
+    if (s.cg_host) (void)hipHostFree(s.cg_host);
+    if (s.scal_host) (void)hipHostFree(s.scal_host);
+    s.cg_host = nullptr;
+    s.scal_host = nullptr;
+    return fail(c, MM_ENOMEM, "device allocation for the derivative workspace failed");
+  }
+  return MM_OK;
+}
+
+// H_eff(m) into s.Hm
+void enqueue_heff_m(mm_ctx* c, Sample& s, const double* m) {
+  EvalOut o;
+  o.H = s.Hm;
+  enqueue_eval(c, s, m, o);
+}
+
+// H_lin[v] (demag + exchange + anisotropy, no Zeeman) into s.Hlin
+void enqueue_hlin(mm_ctx* c, Sample& s, const double* v, const int* done) {
+  EvalOut o;
+  o.H = s.Hlin;
+  o.zeeman = false;
+  o.done = done;
+  enqueue_eval(c, s, v, o);
+}
+
+int read_scal(mm_ctx* c, Sample& s, int n) {
+  HIPCHK(c, hipMemcpyAsync(s.scal_host, s.scal, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
 }
 
 }  // namespace
@@ -625,7 +702,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.has_mat = s.Ms > 0;
   s.evals_total = s.iters_total = 0;
   if (s.has_mat)
-    launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+    launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -658,7 +735,7 @@ int mm_set_material(mm_ctx* c, int sample, double Ms, double A, double Ku, const
     dfree(s.ku_map);
   }
   s.has_mat = true;
-  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -670,7 +747,7 @@ int mm_set_field(mm_ctx* c, int sample, const double* H) {
     return fail(c, MM_EINVAL, "field must be three finite numbers");
   Sample& s = c->smp[sample];
   for (int q = 0; q < 3; ++q) s.H[q] = H[q];
-  if (s.has_mat) launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  if (s.has_mat) launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -679,7 +756,7 @@ int mm_reset(mm_ctx* c, int sample) {
   int rc = check_sample(c, sample, true);
   if (rc != MM_OK) return rc;
   Sample& s = c->smp[sample];
-  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1);
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -714,7 +791,7 @@ int mm_energy(mm_ctx* c, int sample, const double* m, double* E, double* terms4)
   if (rc != MM_OK) return rc;
   if (!m || !E) return fail(c, MM_EINVAL, "null buffer");
   Sample& s = c->smp[sample];
-  launch_reset_state(c->stream, s.st_eval, 0.0, 0.0, 0, 0, 2);
+  launch_reset_state(c->stream, s.st_eval, 0.0, 0.0, 0, 0, 2, s.H);
   EvalOut o;
   o.st_fin = s.st_eval;
   enqueue_eval(c, s, m, o);
@@ -789,21 +866,78 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     if (rc != MM_OK) return rc;
     if (!m[k]) return fail(c, MM_EINVAL, "null magnetisation pointer");
   }
+  for (size_t q = 0; q < (size_t)S * n_fields * 3; ++q)
+    if (!std::isfinite(H[q])) return fail(c, MM_EINVAL, "fields must be finite");
+  if (n_fields == 0) return MM_OK;
+  hipStream_t st = c->stream;
+  const size_t nf3 = (size_t)S * n_fields * 3;
+  double* fields = nullptr;
+  double* mavg = nullptr;
+  long long* its = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    dfree(fields);
+    dfree(mavg);
+    dfree(its);
+  };
+  if (hipMalloc((void**)&fields, nf3 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&mavg, nf3 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&its, (size_t)S * n_fields * sizeof(long long)) != hipSuccess) {
+    cleanup();
+    (void)hipGetLastError();
+    return fail(c, MM_ENOMEM, "device allocation for the sweep tables failed");
+  }
+  HIPCHK(c, hipMemcpyAsync(fields, H, nf3 * sizeof(double), hipMemcpyHostToDevice, st));
+  // every sample runs its whole field list on the device; the host polls
+  for (int k = 0; k < S; ++k) {
+    Sample& s = c->smp[k];
+    for (int q = 0; q < 3; ++q) s.H[q] = H[((size_t)k * n_fields) * 3 + q];
+    launch_reset_state(st, s.st, tau0_of(c, s), tol, (long long)max_iter,
+                       single(c) ? c->stall_iters : 0, 0, s.H);
+    launch_sweep_start(st, s.st, fields + (size_t)k * n_fields * 3, n_fields,
+                       mavg + (size_t)k * n_fields * 3, its + (size_t)k * n_fields, 1.0 / s.N);
+  }
+  std::vector<char> running(S, 1);
+  int left = S;
+  while (left > 0) {
+    for (int k = 0; k < S; ++k) {
+      if (!running[k]) continue;
+      for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, c->smp[k], m[k]);
+    }
+    hipError_t e = hipGetLastError();
+    for (int k = 0; k < S && e == hipSuccess; ++k)
+      if (running[k])
+        e = hipMemcpyAsync(c->smp[k].st_host, c->smp[k].st, sizeof(MinState),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(c, MM_EHIP, std::string("sweep: ") + hipGetErrorString(e));
+    }
+    prof_collect(c);
+    for (int k = 0; k < S; ++k)
+      if (running[k] && c->smp[k].st_host->done != 0) {
+        running[k] = 0;
+        --left;
+      }
+  }
+  std::vector<long long> ih((size_t)S * n_fields);
+  HIPCHK(c, hipMemcpyAsync(m_avg, mavg, nf3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(ih.data(), its, ih.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+  cleanup();
   int worst = MM_OK;
   for (int k = 0; k < S; ++k) {
-    for (int f = 0; f < n_fields; ++f) {
-      const double* h = H + ((size_t)k * n_fields + f) * 3;
-      int rc = mm_set_field(c, k, h);
-      if (rc != MM_OK) return rc;
-      mm_min_result r;
-      rc = run_to_tol(c, c->smp[k], m[k], tol, max_iter, &r);
-      if (rc < 0) return rc;
-      if (rc > worst) worst = rc;
-      if (iters) iters[(size_t)k * n_fields + f] = r.iters;
-      rc = mm_mean(c, k, m[k], m_avg + ((size_t)k * n_fields + f) * 3);
-      if (rc != MM_OK) return rc;
-    }
+    Sample& s = c->smp[k];
+    for (int q = 0; q < 3; ++q) s.H[q] = H[((size_t)k * n_fields + n_fields - 1) * 3 + q];
+    s.evals_total += s.st_host->evals;
+    for (int f = 0; f < n_fields; ++f) s.iters_total += ih[(size_t)k * n_fields + f];
+    const int d = s.st_host->done;
+    if (d == -1) return fail(c, MM_ENONFINITE, "non-finite torque or energy in the sweep");
+    const int code = status_of(d);
+    if (code > worst) worst = code;
   }
+  if (iters)
+    for (size_t q = 0; q < ih.size(); ++q) iters[q] = ih[q];
   return worst;
 }
 
@@ -888,6 +1022,129 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
     case KID_FINISH: b = (double)s.nb3 * kNPartial * 8.0; break;   // per-block sums
   }
   *bytes = b;
+  return MM_OK;
+}
+
+int mm_hessvec(mm_ctx* c, int sample, const double* m, const double* v, double* out) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !v || !out) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  rc = ensure_adj(c, s);
+  if (rc != MM_OK) return rc;
+  enqueue_heff_m(c, s, m);
+  launch_project(c->stream, m, v, s.cp, s.N);     // the operator acts on tangent fields
+  enqueue_hlin(c, s, s.cp, nullptr);
+  launch_hess_apply(c->stream, m, s.Hm, s.Hlin, s.cp, out, s.N, kMu0Host * s.Ms * s.V, nullptr,
+                    nullptr);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_adjoint_solve(mm_ctx* c, int sample, const double* m, const double* rhs, double* lam,
+                     double tol, int64_t max_iter, int64_t* iters, double* resid) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !rhs || !lam || !(tol >= 0) || max_iter < 0) return fail(c, MM_EINVAL, "bad argument");
+  Sample& s = c->smp[sample];
+  rc = ensure_adj(c, s);
+  if (rc != MM_OK) return rc;
+  hipStream_t st = c->stream;
+  enqueue_heff_m(c, s, m);
+  launch_cg_init(st, m, rhs, lam, s.cr, s.cp, s.N, s.partials, s.cg, tol, (long long)max_iter);
+  const double cH = kMu0Host * s.Ms * s.V;
+  const int* done = &s.cg->done;
+  for (;;) {
+    for (int q = 0; q < c->poll_every; ++q) {
+      enqueue_hlin(c, s, s.cp, done);
+      launch_hess_apply(st, m, s.Hm, s.Hlin, s.cp, s.cAp, s.N, cH, s.partials, done);
+      launch_cg_step(st, m, lam, s.cr, s.cp, s.cAp, s.N, s.partials, s.cg);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(s.cg_host, s.cg, sizeof(CGState), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    prof_collect(c);
+    if (s.cg_host->done != 0) break;
+  }
+  const CGState& h = *s.cg_host;
+  if (iters) *iters = h.k;
+  if (resid) *resid = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  if (h.done == -1)
+    return fail(c, MM_ENONFINITE,
+                "conjugate gradients broke down: the Hessian is not positive definite along a "
+                "search direction (m is not a strict local minimum) or a value is not finite");
+  return h.done == 1 ? MM_OK : MM_NOT_CONVERGED;
+}
+
+int mm_param_grads(mm_ctx* c, int sample, const double* m, const double* lam, double* dJ_dA,
+                   double* dJ_dMs, double* dJ_dH, double* dJ_dKu) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !lam) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  rc = ensure_adj(c, s);
+  if (rc != MM_OK) return rc;
+  EvalOut o;
+  o.Hd = s.Hd;
+  o.Hex = s.Hlin;
+  o.unit_A = true;
+  enqueue_eval(c, s, m, o);
+  launch_param_grads(c->stream, m, lam, s.Hd, s.Hlin, s.H, s.u, s.V, dJ_dKu, s.N, s.partials,
+                     s.scal);
+  HIPCHK(c, hipGetLastError());
+  rc = read_scal(c, s, 5);
+  if (rc != MM_OK) return rc;
+  prof_collect(c);
+  if (dJ_dA) *dJ_dA = kMu0Host * s.Ms * s.V * s.scal_host[0];
+  if (dJ_dMs) *dJ_dMs = kMu0Host * s.V * s.scal_host[1];
+  if (dJ_dH)
+    for (int q = 0; q < 3; ++q) dJ_dH[q] = kMu0Host * s.Ms * s.V * s.scal_host[2 + q];
+  return MM_OK;
+}
+
+int mm_energy_grads(mm_ctx* c, int sample, const double* m, double* dU_dm, double* dU_dKu,
+                    double* scal5) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  rc = ensure_adj(c, s);
+  if (rc != MM_OK) return rc;
+  hipStream_t st = c->stream;
+  // energy terms and H_eff(m)
+  launch_reset_state(st, s.st_eval, 0.0, 0.0, 0, 0, 2, s.H);
+  EvalOut o;
+  o.H = s.Hm;
+  o.st_fin = s.st_eval;
+  enqueue_eval(c, s, m, o);
+  launch_energy_grads(st, m, s.Hm, -kMu0Host * s.Ms * s.V, dU_dm, s.u, s.V, dU_dKu, s.N,
+                      s.partials, s.scal);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(s.st_host, s.st_eval, sizeof(MinState), hipMemcpyDeviceToHost, st));
+  rc = read_scal(c, s, 3);
+  if (rc != MM_OK) return rc;
+  const double Ud = s.st_host->eterm[0], Uex = s.st_host->eterm[1], Uz = s.st_host->eterm[3];
+  double dA = 0.0;
+  if (s.A > 0) {
+    dA = Uex / s.A;
+  } else {
+    // U_ex is linear in A: its value at A = 1
+    launch_reset_state(st, s.st_eval, 0.0, 0.0, 0, 0, 2, s.H);
+    EvalOut o1;
+    o1.st_fin = s.st_eval;
+    o1.unit_A = true;
+    enqueue_eval(c, s, m, o1);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(s.st_host, s.st_eval, sizeof(MinState), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    dA = s.st_host->eterm[1];
+  }
+  prof_collect(c);
+  if (scal5) {
+    scal5[0] = (2.0 * Ud + Uz) / s.Ms;
+    scal5[1] = dA;
+    for (int q = 0; q < 3; ++q) scal5[2 + q] = -kMu0Host * s.Ms * s.V * s.scal_host[q];
+  }
   return MM_OK;
 }
 

@@ -263,9 +263,10 @@ k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt
 // LDS: [tensor slab, padded to 1 KiB] [transposes | exchange buffer].
 // ---------------------------------------------------------------------------
 template <typename T, int VL, int NZ, bool HALF>
-__global__ void __launch_bounds__(64 * NZ, 2)
-k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int tstride, T scale,
-          const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+__device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int M,
+                                             const T* __restrict__ Tt, int tstride, T scale,
+                                             const cx<T>* __restrict__ twy,
+                                             const int* __restrict__ done, int kx) {
   if (done != nullptr && *done != 0) return;
   constexpr int n = 64 * VL;
   constexpr int NG = 8 * VL;
@@ -279,7 +280,6 @@ k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int ts
   const int z = threadIdx.x >> 6;
   cx<T>* tbuf = sm + z * wfft_buf<VL, HALF>();   // wave-private transpose buffer
   cx<T>* xbuf = sm;                              // exchange buffer [z][c][DC][64]
-  const int kx = blockIdx.x;
   const size_t slab = (size_t)3 * NZ * ny;
   cx<T>* Ak = A + (size_t)kx * slab;
   // column loads (three components of layer z), one component ahead
@@ -389,6 +389,23 @@ k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int ts
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+template <typename T, int VL, int NZ, bool HALF>
+__global__ void __launch_bounds__(64 * NZ, 2)
+k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int tstride, T scale,
+          const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+  yz_wave_body<T, VL, NZ, HALF>(A, ny, M, Tt, tstride, scale, twy, done, blockIdx.x);
+}
+
+// Batched: items[b] = (sample, kx); all samples share Py and nz.
+template <typename T, int VL, int NZ, bool HALF>
+__global__ void __launch_bounds__(64 * NZ, 2)
+k_yz_wave_b(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  const WorkItem it = items[blockIdx.x];
+  const BatchDesc& d = descs[it.sample];
+  yz_wave_body<T, VL, NZ, HALF>((cx<T>*)d.spec, d.ny, d.M, (const T*)d.Tt, d.tstride, (T)d.scale,
+                                (const cx<T>*)d.twy, &d.st->done, it.block);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,6 +564,46 @@ void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const
     default: yz_dispatch<T, 4>(s, A, ny, Py, M, Tt, tstride, scale, twy, done); break;
   }
 }
+
+template <typename T, int VL, int NZ>
+static void yzb_dispatch(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
+                         int tstride) {
+  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  const size_t ex = (size_t)NZ * 3 * 2 * 64;
+  const size_t tr = (size_t)NZ * wfft_buf<VL, HALF>();
+  const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
+  const size_t lds = tl + (ex > tr ? ex : tr) * sizeof(cx<T>);
+  auto k = k_yz_wave_b<T, VL, NZ, HALF>;
+  set_lds(k, lds);
+  hipLaunchKernelGGL(k, dim3(n_items), dim3(64 * NZ), lds, s, descs, items);
+}
+
+template <typename T, int VL>
+static void yzb_nz(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
+                   int nz, int tstride) {
+  switch (nz) {
+    case 1: yzb_dispatch<T, VL, 1>(s, descs, items, n_items, tstride); break;
+    case 2: yzb_dispatch<T, VL, 2>(s, descs, items, n_items, tstride); break;
+    case 3: yzb_dispatch<T, VL, 3>(s, descs, items, n_items, tstride); break;
+    default: yzb_dispatch<T, VL, 4>(s, descs, items, n_items, tstride); break;
+  }
+}
+
+template <typename T>
+void launch_yz_batched(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
+                       int Py, int nz, int tstride) {
+  switch (Py) {
+    case 64: yzb_nz<T, 1>(s, descs, items, n_items, nz, tstride); break;
+    case 128: yzb_nz<T, 2>(s, descs, items, n_items, nz, tstride); break;
+    case 256: yzb_nz<T, 4>(s, descs, items, n_items, nz, tstride); break;
+    default: yzb_nz<T, 8>(s, descs, items, n_items, nz, tstride); break;
+  }
+}
+
+template void launch_yz_batched<double>(hipStream_t, const BatchDesc*, const WorkItem*, int, int,
+                                        int, int);
+template void launch_yz_batched<float>(hipStream_t, const BatchDesc*, const WorkItem*, int, int,
+                                       int, int);
 
 void launch_twiddles(hipStream_t s, void* tw, int P, bool single) {
   hipLaunchKernelGGL(k_twiddles, dim3((P + 255) / 256), dim3(256), 0, s, tw, P, single ? 1 : 0);

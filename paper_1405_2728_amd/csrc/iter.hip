@@ -102,6 +102,8 @@ __global__ void __launch_bounds__(kXsThreads)
 k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restrict__ Hd_out,
       double* __restrict__ partials, const cx<T>* __restrict__ twx) {
   if (a.done != nullptr && *a.done != 0) return;
+  if (a.Hdyn != nullptr)
+    for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
   __shared__ double scratch[kNPartial * kXsThreads / 64];
@@ -133,7 +135,7 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
   __syncthreads();
   fft_lds<1, VPT>(buf, M, q3, M, twx, Px, tid, nthr);
   const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
-  double part[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double part[kNPartial] = {};
   for (int idx = tid; idx < R * nx; idx += nthr) {
     const int r = idx / nx, x = idx - r * nx;
     const int y = y0 + r;
@@ -151,7 +153,8 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
     }
     local_cell(a, i, hd, bb, part);
   }
-  const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
   block_reduce<kXsThreads>(part, is_max, scratch);
   if (partials != nullptr && tid == 0) {
 #pragma unroll
@@ -173,11 +176,13 @@ template <int VL>
 __host__ __device__ constexpr int wx_region() { return VL * 72 + 8; }
 __device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
 
+// Body of the forward x pass for logical block L (rows z, y0 .. y0+R-1).
 template <typename T, int VL>
-__global__ void __launch_bounds__(kXwThreads)
-k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
-       const MinState* __restrict__ st, int nx, int ny, int nz, int R,
-       cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
+__device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* __restrict__ g,
+                                          double* __restrict__ sbuf,
+                                          const MinState* __restrict__ st, int nx, int ny, int nz,
+                                          int R, cx<T>* __restrict__ out,
+                                          const cx<T>* __restrict__ twx, int L) {
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
@@ -192,8 +197,6 @@ k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict_
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
   T* smr = reinterpret_cast<T*>(smem);
   const int nyb = (ny + R - 1) / R;
-  const int nb = nz * nyb;
-  const int L = xcd_remap(blockIdx.x, nb);
   const int z = L / nyb;
   const int y0 = (L - z * nyb) * R;
   const int rows = min(R, ny - y0);
@@ -295,19 +298,29 @@ k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict_
 
 template <typename T, int VL>
 __global__ void __launch_bounds__(kXwThreads)
-k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ Hd_out,
-        double* __restrict__ partials, const cx<T>* __restrict__ twx) {
+k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
+       const MinState* __restrict__ st, int nx, int ny, int nz, int R,
+       cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
+  xf_w_body<T, VL>(m, g, sbuf, st, nx, ny, nz, R, out, twx, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Body of the inverse x pass with the local terms for logical block L.
+template <typename T, int VL>
+__device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalArgs a, int R,
+                                           double* __restrict__ Hd_out,
+                                           double* __restrict__ partials,
+                                           const cx<T>* __restrict__ twx, int L) {
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
   if (a.done != nullptr && *a.done != 0) return;
+  if (a.Hdyn != nullptr)
+    for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
   __shared__ double scratch[kNPartial * kXwThreads / 64];
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int nyb = (ny + R - 1) / R;
-  const int nb = nz * nyb;
-  const int L = xcd_remap(blockIdx.x, nb);
   const int z = L / nyb;
   const int y0 = (L - z * nyb) * R;
   const int rows = min(R, ny - y0);
@@ -368,7 +381,7 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
   __syncthreads();
   // phase 3: local terms of the rows
   const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
-  double part[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double part[kNPartial] = {};
   {
     constexpr int U = 1;                       // cells per thread per round
     const int total = rows * nx;
@@ -400,12 +413,66 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
       }
     }
   }
-  const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
   block_reduce<kXwThreads>(part, is_max, scratch);
   if (partials != nullptr && tid == 0) {
 #pragma unroll
     for (int v = 0; v < kNPartial; ++v) partials[(size_t)L * kNPartial + v] = part[v];
   }
+}
+
+template <typename T, int VL>
+__global__ void __launch_bounds__(kXwThreads)
+k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ Hd_out,
+        double* __restrict__ partials, const cx<T>* __restrict__ twx) {
+  xil_w_body<T, VL>(in, a, R, Hd_out, partials, twx, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---- batched passes: one launch covers the blocks of several samples ---------
+// items[b] names the sample and its logical block; every sample of a launch
+// has the same transform length and rows per block.
+template <typename T, int VL>
+__global__ void __launch_bounds__(kXwThreads)
+k_xf_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  const WorkItem it = items[blockIdx.x];
+  const BatchDesc& d = descs[it.sample];
+  xf_w_body<T, VL>(d.m, d.g, d.s, d.st, d.nx, d.ny, d.nz, d.R, (cx<T>*)d.spec,
+                   (const cx<T>*)d.twx, it.block);
+}
+
+template <typename T, int VL>
+__global__ void __launch_bounds__(kXwThreads)
+k_xil_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  const WorkItem it = items[blockIdx.x];
+  const BatchDesc& d = descs[it.sample];
+  LocalArgs a;
+  a.m = d.m;
+  a.Hd = nullptr;
+  a.g = d.g;
+  a.s = d.s;
+  a.Hout = nullptr;
+  a.Hex_out = nullptr;
+  a.Han_out = nullptr;
+  a.ku_map = d.ku_map;
+  a.nx = d.nx;
+  a.ny = d.ny;
+  a.nz = d.nz;
+  a.cx = d.cx;
+  a.cy = d.cy;
+  a.cz = d.cz;
+  a.ku = d.ku;
+  a.kan = d.kan;
+  for (int c = 0; c < 3; ++c) {
+    a.u[c] = d.u[c];
+    a.H[c] = 0.0;
+  }
+  a.Hdyn = d.st->H;
+  a.partials = d.partials;
+  a.st = d.st;
+  a.done = &d.st->done;
+  xil_w_body<T, VL>((const cx<T>*)d.spec, a, d.R, nullptr, d.partials, (const cx<T>*)d.twx,
+                    it.block);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,6 +586,36 @@ void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R
   }
 }
 
+template <typename T, int VL>
+static void xb_launch(hipStream_t s, bool inverse, const BatchDesc* descs, const WorkItem* items,
+                      int n_items, int R) {
+  const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
+  if (inverse) {
+    auto k = k_xil_wb<T, VL>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(n_items), dim3(192 * R), lds, s, descs, items);
+  } else {
+    auto k = k_xf_wb<T, VL>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(n_items), dim3(192 * R), lds, s, descs, items);
+  }
+}
+
+template <typename T>
+void launch_x_batched(hipStream_t s, bool inverse, const BatchDesc* descs, const WorkItem* items,
+                      int n_items, int M, int R) {
+  switch (M) {
+    case 64: xb_launch<T, 1>(s, inverse, descs, items, n_items, R); break;
+    case 128: xb_launch<T, 2>(s, inverse, descs, items, n_items, R); break;
+    case 256: xb_launch<T, 4>(s, inverse, descs, items, n_items, R); break;
+    default: xb_launch<T, 8>(s, inverse, descs, items, n_items, R); break;
+  }
+}
+
+template void launch_x_batched<double>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
+                                       int, int);
+template void launch_x_batched<float>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
+                                      int, int);
 template void launch_xf<double>(hipStream_t, double*, const double*, double*, const MinState*, int,
                                 int, int, int, int, void*, const void*);
 template void launch_xf<float>(hipStream_t, double*, const double*, double*, const MinState*, int,

@@ -21,17 +21,20 @@ namespace mmk {
 __global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
   __shared__ double scratch[kNPartial * (kLocalThreads / 64)];
   if (a.done != nullptr && *a.done != 0) return;
+  if (a.Hdyn != nullptr)
+    for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
   const int N = a.nx * a.ny * a.nz;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
-  double part[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double part[kNPartial] = {};
   if (i < N) {
     double hd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) hd[c] = a.Hd[(size_t)c * N + i];
     local_cell(a, i, hd, bb, part);
   }
-  const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
   block_reduce<kLocalThreads>(part, is_max, scratch);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -45,16 +48,40 @@ __global__ void __launch_bounds__(1024) k_finish(const double* __restrict__ part
                                                  MinState* __restrict__ st, double Ms, double V) {
   __shared__ double scratch[kNPartial * 1024 / 64];
   if (st->done != 0) return;
-  double v[kNPartial] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[kNPartial] = {};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
-    for (int q = 0; q < kNPartial - 1; ++q) v[q] += partials[(size_t)b * kNPartial + q];
-    v[7] = fmax(v[7], partials[(size_t)b * kNPartial + 7]);
+    for (int q = 0; q < kNPartial; ++q) {
+      const double x = partials[(size_t)b * kNPartial + q];
+      v[q] = q == kPartMax ? fmax(v[q], x) : v[q] + x;
+    }
   }
-  const bool is_max[kNPartial] = {false, false, false, false, false, false, false, true};
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
   block_reduce<1024>(v, is_max, scratch);
   if (threadIdx.x != 0) return;
   finish_decision(st, v, Ms, V);
+}
+
+// Batched: block b finishes sample b of the table.
+__global__ void __launch_bounds__(1024) k_finish_b(const BatchDesc* __restrict__ descs) {
+  __shared__ double scratch[kNPartial * 1024 / 64];
+  const BatchDesc& d = descs[blockIdx.x];
+  MinState* st = d.st;
+  if (st->done != 0) return;
+  double v[kNPartial] = {};
+  for (int b = threadIdx.x; b < d.nb3; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) {
+      const double x = d.partials[(size_t)b * kNPartial + q];
+      v[q] = q == kPartMax ? fmax(v[q], x) : v[q] + x;
+    }
+  }
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
+  block_reduce<1024>(v, is_max, scratch);
+  if (threadIdx.x != 0) return;
+  finish_decision(st, v, d.Ms, d.V);
 }
 
 // Apply a pending midpoint update (eq. (7)) to m and store s = m+ - m.
@@ -110,7 +137,7 @@ __global__ void __launch_bounds__(256) k_mean_finish(const double* __restrict__ 
 }
 
 __global__ void k_reset_state(MinState* st, double tau0, double tol, long long max_iter,
-                              long long stall_iters, int mode) {
+                              long long stall_iters, int mode, double hx, double hy, double hz) {
   MinState z;
   z.tau = tau0;
   z.torque = 0.0;
@@ -130,7 +157,33 @@ __global__ void k_reset_state(MinState* st, double tau0, double tol, long long m
   z.last_tau = tau0;
   z.last_k = 0;
   z.pending = 0;
+  z.H[0] = hx;
+  z.H[1] = hy;
+  z.H[2] = hz;
+  z.sweep = 0;
+  z.field = 0;
+  z.n_fields = 0;
+  z.fields = nullptr;
+  z.mavg_out = nullptr;
+  z.iters_out = nullptr;
+  z.worst = 1;
+  z.inv_N = 0.0;
   *st = z;
+}
+
+// Turn a freshly reset state into a sweep over fields[0 .. n_fields).
+__global__ void k_sweep_start(MinState* st, const double* fields, int n_fields, double* mavg_out,
+                              long long* iters_out, double inv_N) {
+  st->sweep = 1;
+  st->field = 0;
+  st->n_fields = n_fields;
+  st->fields = fields;
+  st->mavg_out = mavg_out;
+  st->iters_out = iters_out;
+  st->worst = 1;
+  st->inv_N = inv_N;
+  for (int c = 0; c < 3; ++c) st->H[c] = fields[c];
+  if (n_fields <= 0) st->done = 1;
 }
 
 // Switch the mode of a run without touching its BB history (clears done).
@@ -140,9 +193,15 @@ __global__ void k_set_mode(MinState* st, int mode) {
 }
 
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
-                        long long stall_iters, int mode) {
+                        long long stall_iters, int mode, const double H[3]) {
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(1), 0, s, st, tau0, tol, max_iter, stall_iters,
-                     mode);
+                     mode, H[0], H[1], H[2]);
+}
+
+void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,
+                        double* mavg_out, long long* iters_out, double inv_N) {
+  hipLaunchKernelGGL(k_sweep_start, dim3(1), dim3(1), 0, s, st, fields, n_fields, mavg_out,
+                     iters_out, inv_N);
 }
 
 void launch_clear_pending(hipStream_t s, MinState* st) {
@@ -163,6 +222,10 @@ void launch_local(hipStream_t s, const LocalArgs& a) {
 void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
                    double V) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partials, nblocks, st, Ms, V);
+}
+
+void launch_finish_batched(hipStream_t s, const BatchDesc* descs, int n_samples) {
+  hipLaunchKernelGGL(k_finish_b, dim3(n_samples), dim3(1024), 0, s, descs);
 }
 
 void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,

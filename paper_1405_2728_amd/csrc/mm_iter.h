@@ -84,6 +84,9 @@ __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const do
   part[4] += mi[0] * hex[0] + mi[1] * hex[1] + mi[2] * hex[2];
   part[5] += d.ku * mu * mu;
   part[6] += mi[0] * a.H[0] + mi[1] * a.H[1] + mi[2] * a.H[2];
+  part[8] += mi[0];
+  part[9] += mi[1];
+  part[10] += mi[2];
   const double ax = mi[1] * h[2] - mi[2] * h[1];
   const double ay = mi[2] * h[0] - mi[0] * h[2];
   const double az = mi[0] * h[1] - mi[1] * h[0];
@@ -138,16 +141,39 @@ __device__ __forceinline__ void finish_decision(MinState* st, const double v[kNP
   }
   const long long k = st->k;
   if (st->mode == 0) {
-    if (T < st->tol) { st->done = 1; return; }
-    if (k >= st->max_iter) { st->done = 2; return; }
-    if (st->stall_iters > 0) {
+    int end = 0;
+    if (T < st->tol) end = 1;
+    else if (k >= st->max_iter) end = 2;
+    else if (st->stall_iters > 0) {
       if (T < st->best_torque) {
         st->best_torque = T;
         st->best_k = k;
       } else if (k - st->best_k >= st->stall_iters) {
-        st->done = 3;
-        return;
+        end = 3;
       }
+    }
+    if (end != 0) {
+      if (st->sweep == 0) {
+        st->done = end;
+      } else {
+        // record this field, then continue with the next one from the same m
+        const int f = st->field;
+        for (int c = 0; c < 3; ++c) st->mavg_out[3 * f + c] = v[8 + c] * st->inv_N;
+        st->iters_out[f] = k;
+        if (end > st->worst) st->worst = end;
+        st->field = f + 1;
+        if (f + 1 >= st->n_fields) {
+          st->done = st->worst;
+        } else {
+          for (int c = 0; c < 3; ++c) st->H[c] = st->fields[3 * (f + 1) + c];
+          st->k = 0;
+          st->tau = st->tau0;
+          st->last_tau = st->tau0;
+          st->best_torque = __builtin_huge_val();
+          st->best_k = 0;
+        }
+      }
+      return;
     }
   }
   if (k > 0) {

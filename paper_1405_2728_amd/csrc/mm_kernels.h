@@ -30,6 +30,55 @@ struct MinState {
   double last_tau;     // tau used by the most recent update (for step info)
   long long last_k;    // k index of the most recent evaluation
   int pending;         // 1: an update with last_tau is due before the next evaluation
+  double H[3];         // external field of the current run (A/m)
+  // Hysteresis sweep on the device (sweep = 1): when a field's run ends
+  // (stop rule, max_iter or stall) its mean magnetisation and update count
+  // are recorded, the next field is applied and the BB state restarts from
+  // the same m; after the last field done = the worst status of the fields.
+  int sweep;
+  int field, n_fields;
+  const double* fields;    // device [n_fields][3]
+  double* mavg_out;        // device [n_fields][3]
+  long long* iters_out;    // device [n_fields]
+  int worst;               // 1 converged, 2 max_iter, 3 stalled (worst so far)
+  double inv_N;            // 1 / cells, for the mean
+};
+
+// Conjugate-gradient state of an adjoint solve, resident in device memory.
+struct CGState {
+  double bb;           // |P rhs|^2
+  double rr;           // |r_k|^2
+  double pAp;          // p_k . Hess p_k
+  double alpha, beta;
+  double tol2;         // stop when rr <= tol2 bb
+  long long k, max_iter;
+  int done;            // 0 running; 1 converged; 2 max_iter; -1 breakdown or non-finite
+};
+
+// One sample of a batched launch (device table): its buffers, sizes and
+// material constants.  The external field is read from st->H.
+struct BatchDesc {
+  double* m;
+  double* g;
+  double* s;
+  void* spec;            // spectrum A[kx][z][y][c] (T complex)
+  const void* Tt;        // thin-film tensor (T)
+  const void* twx;       // twiddles, length Px (T complex)
+  const void* twy;       // twiddles, length Py (T complex)
+  MinState* st;
+  double* partials;      // [nb3][kNPartial]
+  const double* ku_map;  // NULL: scalar ku
+  int nx, ny, nz, M, Py, R, tstride, nb3;
+  double cx, cy, cz;     // 2A/(mu0 Ms D^2)
+  double ku, kan;        // scalar Ku; 2/(mu0 Ms)
+  double u[3];
+  double scale;          // -Ms/(M Py)
+  double Ms, V;
+};
+// A block of a batched launch: sample index and logical block of its pass.
+struct WorkItem {
+  int sample;
+  int block;
 };
 
 // Gauss-Legendre rules used by the far-field tensor (nodes on [-1, 1]).
@@ -92,6 +141,15 @@ inline int thin_tensor_stride(int nz, int Py, bool single) {
   return (e + q - 1) / q * q;
 }
 bool yz_thin_fits(int nz, int Py, bool single);
+bool yz_wave_ok(int nz, int Py);
+// batched passes (all items of a launch share M and R, resp. Py and nz)
+template <typename T>
+void launch_x_batched(hipStream_t s, bool inverse, const BatchDesc* descs, const WorkItem* items,
+                      int n_items, int M, int R);
+template <typename T>
+void launch_yz_batched(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
+                       int Py, int nz, int tstride);
+void launch_finish_batched(hipStream_t s, const BatchDesc* descs, int n_samples);
 
 // ---- local terms, step size, update -----------------------------------------
 struct LocalArgs {
@@ -107,12 +165,16 @@ struct LocalArgs {
   double cx, cy, cz;    // 2A/(mu0 Ms D^2) per axis
   double ku, kan;       // scalar Ku; 2/(mu0 Ms)
   double u[3], H[3];
-  double* partials;     // [nblocks][8]
+  const double* Hdyn;   // device field overriding H (NULL: use H)
+  double* partials;     // [nblocks][kNPartial]
   const MinState* st;   // NULL outside the minimiser
   const int* done;      // NULL outside the minimiser
 };
 constexpr int kLocalThreads = 256;
-constexpr int kNPartial = 8;
+// per-block sums: [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext, max |g|^2,
+// sum m_x, sum m_y, sum m_z]; entry kPartMax is a maximum, the others sums
+constexpr int kNPartial = 11;
+constexpr int kPartMax = 7;
 int local_blocks(int N);
 void launch_local(hipStream_t s, const LocalArgs& a);
 void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
@@ -120,7 +182,9 @@ void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState*
 void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
                    const MinState* st);
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
-                        long long stall_iters, int mode);
+                        long long stall_iters, int mode, const double H[3]);
+void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,
+                        double* mavg_out, long long* iters_out, double inv_N);
 void launch_set_mode(hipStream_t s, MinState* st, int mode);
 void launch_clear_pending(hipStream_t s, MinState* st);
 // fused x passes of the thin-film iteration
@@ -133,5 +197,23 @@ template <typename T>
 void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,
                 double* partials, const void* twx);
 void launch_mean(hipStream_t s, const double* m, int N, double* partials, double* out3);
+
+// ---- derivatives (adjoint.hip) ------------------------------------------------
+int adj_blocks(int N);
+void launch_cg_init(hipStream_t s, const double* m, const double* rhs, double* x, double* r,
+                    double* p, int N, double* partials, CGState* cg, double tol,
+                    long long max_iter);
+void launch_hess_apply(hipStream_t s, const double* m, const double* Hm, const double* Hlin,
+                       const double* v, double* out, int N, double c, double* partials,
+                       const int* done);
+void launch_cg_step(hipStream_t s, const double* m, double* x, double* r, double* p,
+                    const double* Ap, int N, double* partials, CGState* cg);
+void launch_project(hipStream_t s, const double* m, const double* v, double* out, int N);
+void launch_param_grads(hipStream_t s, const double* m, const double* lam, const double* Hd,
+                        const double* Hex1, const double H[3], const double u[3], double V,
+                        double* dKu, int N, double* partials, double* out5);
+void launch_energy_grads(hipStream_t s, const double* m, const double* H, double c, double* dm,
+                         const double u[3], double V, double* dKu, int N, double* partials,
+                         double* out3);
 
 }  // namespace mmk

@@ -69,6 +69,11 @@ SHAPES = [
     ((32, 16, 1), (5e-9, 5e-9, 5e-9)),
     ((64, 9, 1), (3e-9, 5e-9, 4e-9)),
     ((13, 40, 2), (5e-9, 5e-9, 5e-9)),
+    # every wave x-pass length with 4 rows per block (M = 64 .. 256) and 2 (M = 512)
+    ((200, 100, 2), (5e-9, 5e-9, 5e-9)),
+    ((150, 37, 1), (4e-9, 5e-9, 6e-9)),
+    ((90, 7, 3), (5e-9, 5e-9, 5e-9)),
+    ((300, 5, 1), (5e-9, 5e-9, 5e-9)),
 ]
 
 
