@@ -83,6 +83,7 @@ struct mm_ctx {
   int poll_every = 32;
   long long stall_iters = 500;
   int use_graph = 0;
+  int batched = 1;              // sweeps of several samples share launches
   int path_pref = 0;            // 0 automatic, 1 thin-film, 2 full 3-D
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
@@ -495,6 +496,157 @@ void enqueue_iteration(mm_ctx* c, Sample& s, double* m) {
 
 double tau0_of(const mm_ctx* c, const Sample& s) { return c->tau0 > 0 ? c->tau0 : 1e-3 / s.Ms; }
 
+// ---- batched sweep ---------------------------------------------------------------
+// Samples whose passes have wave-FFT kernels (thin films, x and y lengths in
+// 64..512) run together: one launch per group of equal transform lengths
+// covers the blocks of all of them, and one finish launch covers all.
+struct BatchGroup {
+  int a = 0, b = 0, t = 0;    // x: (M, R); yz: (Py, nz, tstride)
+  int off = 0, n = 0;         // range in the item table
+};
+
+struct BatchPlan {
+  std::vector<int> members;               // sample indices, in table order
+  std::vector<BatchGroup> xg, yg;
+  BatchDesc* descs = nullptr;
+  WorkItem* items = nullptr;
+  hipGraphExec_t graph = nullptr;
+  ~BatchPlan() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (descs) (void)hipFree(descs);
+    if (items) (void)hipFree(items);
+  }
+};
+
+bool batchable(const Sample& s) {
+  return s.path == PATH_THIN && (s.M == 64 || s.M == 128 || s.M == 256 || s.M == 512) &&
+         yz_wave_ok(s.nz, s.Py);
+}
+
+// XCD-aware order: hardware block b takes logical item xcd_remap(b, n), so
+// each XCD works through a contiguous run of logical items (whole samples).
+void xcd_order(std::vector<WorkItem>& v) {
+  const int n = (int)v.size();
+  const int full = (n / 8) * 8;
+  std::vector<WorkItem> o(v.size());
+  for (int b = 0; b < n; ++b) {
+    const int L = b >= full ? b : (b & 7) * (n / 8) + (b >> 3);
+    o[b] = v[L];
+  }
+  v.swap(o);
+}
+
+int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
+  std::vector<BatchDesc> d;
+  for (int k = 0; k < (int)c->smp.size(); ++k) {
+    Sample& s = c->smp[k];
+    if (!batchable(s)) continue;
+    BatchDesc b;
+    const LocalArgs a = local_args(s);
+    b.m = m[k];
+    b.g = s.g;
+    b.s = s.s;
+    b.spec = s.spec;
+    b.Tt = s.Tt;
+    b.twx = s.twx;
+    b.twy = s.twy;
+    b.st = s.st;
+    b.partials = s.partials;
+    b.ku_map = s.ku_map;
+    b.nx = s.nx;
+    b.ny = s.ny;
+    b.nz = s.nz;
+    b.M = s.M;
+    b.Py = s.Py;
+    b.R = s.R3;
+    b.tstride = s.tstride;
+    b.nb3 = s.nb3;
+    b.cx = a.cx;
+    b.cy = a.cy;
+    b.cz = a.cz;
+    b.ku = a.ku;
+    b.kan = a.kan;
+    for (int q = 0; q < 3; ++q) b.u[q] = a.u[q];
+    b.scale = -s.Ms / ((double)s.M * (double)s.Py);
+    b.Ms = s.Ms;
+    b.V = s.V;
+    P.members.push_back(k);
+    d.push_back(b);
+  }
+  if (d.empty()) return MM_OK;
+  std::vector<WorkItem> all;
+  auto add_groups = [&](bool x, std::vector<BatchGroup>& groups) {
+    std::vector<BatchGroup> keys;
+    for (int i = 0; i < (int)d.size(); ++i) {
+      BatchGroup g;
+      if (x) { g.a = d[i].M; g.b = d[i].R; }
+      else { g.a = d[i].Py; g.b = d[i].nz; g.t = d[i].tstride; }
+      bool seen = false;
+      for (auto& q : keys) seen = seen || (q.a == g.a && q.b == g.b && q.t == g.t);
+      if (!seen) keys.push_back(g);
+    }
+    for (auto g : keys) {
+      std::vector<WorkItem> v;
+      for (int i = 0; i < (int)d.size(); ++i) {
+        const bool match = x ? (d[i].M == g.a && d[i].R == g.b)
+                             : (d[i].Py == g.a && d[i].nz == g.b && d[i].tstride == g.t);
+        if (!match) continue;
+        const int nb = x ? d[i].nb3 : d[i].M + 1;
+        for (int blk = 0; blk < nb; ++blk) v.push_back({i, blk});
+      }
+      xcd_order(v);
+      g.off = (int)all.size();
+      g.n = (int)v.size();
+      all.insert(all.end(), v.begin(), v.end());
+      groups.push_back(g);
+    }
+  };
+  add_groups(true, P.xg);
+  add_groups(false, P.yg);
+  if (hipMalloc((void**)&P.descs, d.size() * sizeof(BatchDesc)) != hipSuccess ||
+      hipMalloc((void**)&P.items, all.size() * sizeof(WorkItem)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, MM_ENOMEM, "device allocation for the batch tables failed");
+  }
+  HIPCHK(c, hipMemcpyAsync(P.descs, d.data(), d.size() * sizeof(BatchDesc), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(P.items, all.data(), all.size() * sizeof(WorkItem),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+// One iteration of every batched sample.
+void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
+  hipStream_t st = c->stream;
+  const bool sp = single(c);
+  {
+    Timer t(c, KID_XF);
+    for (const auto& g : P.xg) {
+      if (sp) launch_x_batched<float>(st, false, P.descs, P.items + g.off, g.n, g.a, g.b);
+      else launch_x_batched<double>(st, false, P.descs, P.items + g.off, g.n, g.a, g.b);
+    }
+  }
+  {
+    Timer t(c, KID_YZ);
+    for (const auto& g : P.yg) {
+      if (sp) launch_yz_batched<float>(st, P.descs, P.items + g.off, g.n, g.a, g.b, g.t);
+      else launch_yz_batched<double>(st, P.descs, P.items + g.off, g.n, g.a, g.b, g.t);
+    }
+  }
+  {
+    Timer t(c, KID_XIL);
+    for (const auto& g : P.xg) {
+      if (sp) launch_x_batched<float>(st, true, P.descs, P.items + g.off, g.n, g.a, g.b);
+      else launch_x_batched<double>(st, true, P.descs, P.items + g.off, g.n, g.a, g.b);
+    }
+  }
+  {
+    Timer t(c, KID_FINISH);
+    launch_finish_batched(st, P.descs, (int)P.members.size());
+  }
+}
+
 int status_of(int done) {
   switch (done) {
     case 1: return MM_OK;
@@ -897,13 +1049,52 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     launch_sweep_start(st, s.st, fields + (size_t)k * n_fields * 3, n_fields,
                        mavg + (size_t)k * n_fields * 3, its + (size_t)k * n_fields, 1.0 / s.N);
   }
+  BatchPlan plan;
+  std::vector<char> in_batch(S, 0);
+  if (c->batched && S > 1) {
+    int rc = build_batch(c, m, plan);
+    if (rc != MM_OK) {
+      cleanup();
+      return rc;
+    }
+    if (plan.members.size() < 2) plan.members.clear();
+    for (int k : plan.members) in_batch[k] = 1;
+  }
+  // a captured batch of iterations is replayed when the stream allows it
+  const bool graph = c->use_graph && c->stream != nullptr && c->prof == 0 && !plan.members.empty();
   std::vector<char> running(S, 1);
   int left = S;
+  int batch_left = (int)plan.members.size();
+  int polls = 0;
   while (left > 0) {
+    if (batch_left > 0) {
+      // the first batch runs eagerly (kernel attributes are set there); later
+      // batches replay one captured graph of poll_every iterations
+      if (graph && polls > 0) {
+        if (!plan.graph) {
+          hipGraph_t g = nullptr;
+          hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+          if (e == hipSuccess) {
+            for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
+            e = hipStreamEndCapture(c->stream, &g);
+          }
+          if (e == hipSuccess) e = hipGraphInstantiate(&plan.graph, g, nullptr, nullptr, 0);
+          if (g) (void)hipGraphDestroy(g);
+          if (e != hipSuccess) {
+            cleanup();
+            return fail(c, MM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+          }
+        }
+        HIPCHK(c, hipGraphLaunch(plan.graph, c->stream));
+      } else {
+        for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
+      }
+    }
     for (int k = 0; k < S; ++k) {
-      if (!running[k]) continue;
+      if (!running[k] || in_batch[k]) continue;
       for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, c->smp[k], m[k]);
     }
+    ++polls;
     hipError_t e = hipGetLastError();
     for (int k = 0; k < S && e == hipSuccess; ++k)
       if (running[k])
@@ -919,6 +1110,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
       if (running[k] && c->smp[k].st_host->done != 0) {
         running[k] = 0;
         --left;
+        if (in_batch[k]) --batch_left;
       }
   }
   std::vector<long long> ih((size_t)S * n_fields);
@@ -955,6 +1147,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->stall_iters = (long long)value;
   } else if (!std::strcmp(key, "use_graph")) {
     c->use_graph = value != 0.0;
+  } else if (!std::strcmp(key, "batched")) {
+    c->batched = value != 0.0;
   } else if (!std::strcmp(key, "demag_path")) {
     if (value != 0 && value != 1 && value != 2) return fail(c, MM_EINVAL, "demag_path is 0, 1 or 2");
     c->path_pref = (int)value;

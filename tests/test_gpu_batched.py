@@ -1,0 +1,110 @@
+"""Batched sweeps: several samples of different shapes share launches (one
+per group of equal transform lengths) and run their field lists on the
+device.  The batched kernels run the same per-block code with the same
+reduction order as the per-sample path, so the results must be bitwise
+identical to it; replays of a captured graph likewise."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fields as of, minimizer as om
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1405_2728_amd import _build
+    if not os.path.exists(_build.lib_path()):
+        _build.build(verbose=False)
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# thin wave-eligible shapes of several groups, one Stockham-path shape and one
+# 3-D shape (those two run per sample inside the same sweep)
+SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (20, 10, 1),
+          (10, 8, 6)]
+
+
+def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4):
+    from paper_1405_2728_amd import Context
+    stream = torch.cuda.Stream() if graph else None
+    ctx = Context(prec, n_samples=len(shapes), stream=stream)
+    ctx.set_option("batched", 1 if batched else 0)
+    ctx.set_option("use_graph", 1 if graph else 0)
+    ctx.set_option("poll_every", 8)
+    rng = np.random.default_rng(31)
+    ms, H = [], []
+    for k, n in enumerate(shapes):
+        ctx.set_geometry(k, *n, 5e-9, 5e-9, 5e-9)
+        ctx.set_material(k, 8e5, 1.3e-11, float(rng.uniform(0, 2e3)), (1.0, 0.0, 0.0))
+        h = synth.tilted(float(rng.uniform(0, 90)))
+        ms.append(torch.tensor(synth.uniform_with_noise(h, *n, 1e-3, rng), device="cuda"))
+        H.append(np.linspace(40, -40, n_fields)[:, None] * synth.MT * h[None, :])
+    if stream is not None:
+        with torch.cuda.stream(stream):
+            mavg, iters, rc = ctx.hysteresis_sweep(ms, np.array(H), tol=1e-6)
+        stream.synchronize()
+    else:
+        mavg, iters, rc = ctx.hysteresis_sweep(ms, np.array(H), tol=1e-6)
+    out = [m.cpu().numpy() for m in ms]
+    ctx.close()
+    return mavg, iters, rc, out, H
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_equals_per_sample(torch_cuda, prec):
+    torch = torch_cuda
+    say("case batched vs per-sample", prec)
+    a = run(torch, prec, batched=False)
+    b = run(torch, prec, batched=True)
+    say("  iterations", b[1].tolist())
+    assert a[2] == b[2] == 0
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
+
+
+def test_graph_replays_equal_eager(torch_cuda):
+    torch = torch_cuda
+    say("case graph replay")
+    a = run(torch, "fp64", batched=True, graph=False)
+    b = run(torch, "fp64", batched=True, graph=True)
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
+
+
+def test_batched_sweep_stationary(torch_cuda):
+    """Each sample's final state is stationary for the oracle at its last
+    field (cross-stationarity, tol 1e-6)."""
+    torch = torch_cuda
+    say("case batched stationarity")
+    shapes = [(64, 32, 1), (70, 33, 2), (20, 10, 1)]
+    mavg, iters, rc, out, H = run(torch, "fp64", batched=True, shapes=shapes, n_fields=3)
+    assert rc == 0
+    rng = np.random.default_rng(31)
+    for k, n in enumerate(shapes):
+        ku = float(rng.uniform(0, 2e3))
+        rng.uniform(0, 90)
+        synth.uniform_with_noise((1, 0, 0), *n, 1e-3, rng)   # keep the draw order of run()
+        P = of.Problem(*n, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=ku, u=(1, 0, 0),
+                       H_ext=H[k][-1])
+        T = om.torque(out[k], P.heff(out[k]), P.Ms)
+        say("  sample", k, "oracle torque", T)
+        assert T < 1e-6 * 1.001
+        assert np.allclose(mavg[k, -1], out[k].reshape(3, -1).mean(axis=1), atol=1e-12)
