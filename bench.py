@@ -14,6 +14,14 @@ clock starts.
 With --workload cube the same measurement runs on the 128^3 cube of 2 nm
 cells (full 3-D demag path, random start, 60 mT at 2 degrees from z).
 
+The line also carries "batched": 64 uneven thin platelets (64..256 x
+32..128 x 1..2 cells) swept through every 10th field of their +-40 mT loop,
+once with all samples sharing launches (captured graph) and once sample by
+sample, both in FP64: summed minimiser iterations per second and the
+speed-up.  --workload batched runs that alone on the whole loop (81 fields);
+--workload adjoint times the implicit gradient of the 200 x 100 x 2 film
+with a per-cell Ku map (conjugate gradients + parameter gradients).
+
 Prints one JSON line.
 """
 
@@ -36,6 +44,7 @@ WORKLOADS = {
     "cube": (2, 3, "cube 128^3 cells of 2 nm, full 3-D demag, BB midpoint minimiser, "
                    "random start, 60 mT at 2 deg from z", [256, 256, 256]),
 }
+EXTRA_WORKLOADS = ("batched", "adjoint")
 
 
 def parse():
@@ -44,7 +53,9 @@ def parse():
     p.add_argument("--steps", type=int, default=400)
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
-    p.add_argument("--workload", choices=sorted(WORKLOADS), default="film")
+    p.add_argument("--workload", choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS),
+                   default="film")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-iters", type=int, default=20)
     p.add_argument("--quick", action="store_true",
@@ -102,6 +113,63 @@ def stored_traffic(prec, kernel, workload):
     return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
+def run_batched(torch, batched, field_step=10, prec="fp64"):
+    """Sweep the 64 platelets through every field_step-th field of their
+    loop; returns (summed iterations, seconds, status)."""
+    import synth
+    from paper_1405_2728_amd import Context
+    plats = synth.batched_platelets()
+    stream = torch.cuda.Stream()
+    ctx = Context(prec, n_samples=len(plats), stream=stream)
+    ctx.set_option("batched", 1 if batched else 0)
+    ctx.set_option("use_graph", 1 if batched else 0)
+    ms, H = [], []
+    for k, p in enumerate(plats):
+        ctx.set_geometry(k, *p["n"], *p["d"])
+        ctx.set_material(k, p["Ms"], p["A"], p["Ku"], p["u"])
+        ms.append(torch.tensor(p["m0"], device="cuda"))
+        H.append(p["fields"][::field_step])
+    H = np.array(H)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        mavg, iters, rc = ctx.hysteresis_sweep(ms, H, tol=plats[0]["tol"])
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+    ctx.close()
+    return int(iters.sum()), dt, rc, H.shape[1]
+
+
+def run_adjoint(torch):
+    """200x100x2 film with a Ku map: sweep 0..-5 mT (tol 1e-10), then the
+    gradient of <m_x> by the adjoint (timed)."""
+    import synth
+    from paper_1405_2728_amd import Context
+    w = synth.workload(4)
+    ctx = Context("fp64")
+    ctx.set_geometry(0, *w["n"], *w["d"])
+    ctx.set_material(0, w["Ms"], w["A"], 0.0, w["u"],
+                     torch.tensor(w["Ku"], dtype=torch.float64, device="cuda"))
+    m = torch.tensor(w["m0"], device="cuda")
+    t0 = time.perf_counter()
+    _, iters, rc = ctx.hysteresis_sweep([m], w["fields"], tol=1e-10)
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t0
+    dJ = torch.zeros_like(m)
+    dJ[0] = 1.0 / m[0].numel()
+    ctx.adjoint_solve(0, m, dJ, tol=1e-10)           # warm-up (workspace allocation)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, it, res, rc2 = ctx.adjoint_solve(0, m, dJ, tol=1e-10)
+    g = ctx.param_grads(0, m, lam)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    ctx.close()
+    return {"sweep_iters": int(iters.sum()), "sweep_s": t_sweep, "cg_iterations": it,
+            "cg_residual": res, "adjoint_s": t_adj, "cg_iters_per_s": it / t_adj,
+            "dJ_dA": g["A"], "dJ_dMs": g["Ms"], "status": [int(rc), int(rc2)]}
+
+
 def cpu_baseline(w, iters, field, label):
     from oracle import fields as of, minimizer as om
     P = of.Problem(*w["n"], *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"],
@@ -132,6 +200,23 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 8 * n, "launches": 5}))
+        return
+    if a.workload == "batched":
+        ib, tb, rcb, nf = run_batched(torch, True, field_step=1)
+        iseq, tseq, rcs, _ = run_batched(torch, False, field_step=1)
+        print(json.dumps({"metric": "summed minimiser iterations/s, 64 uneven platelets, "
+                                    "81-field loop", "value": ib / tb, "unit": "iters/s",
+                          "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+                          "data": "synthetic", "batched_s": tb, "iterations": ib,
+                          "per_sample": {"value": iseq / tseq, "seconds": tseq,
+                                         "iterations": iseq},
+                          "speedup": (ib / tb) / (iseq / tseq), "status": [rcb, rcs]}))
+        return
+    if a.workload == "adjoint":
+        r = run_adjoint(torch)
+        r.update({"metric": "implicit gradient of <m_x>, 200x100x2 film with Ku map",
+                  "n_gpus": 1, "dtype": "f64", "data": "synthetic"})
+        print(json.dumps(r))
         return
     wid, field, wdesc, padded = WORKLOADS[a.workload]
     w = synth.workload(wid)
@@ -188,6 +273,16 @@ def main():
                 "kernel_avg_us_all_timed": {k: 1e3 * v[0] / max(v[1], 1)
                                             for k, v in other_prof.items() if v[1] > 0}},
     }
+    if not a.no_batched:
+        ib, tb, rcb, nf = run_batched(torch, True)
+        iseq, tseq, rcs, _ = run_batched(torch, False)
+        out["batched"] = {"workload": "64 uneven platelets (64..256 x 32..128 x 1..2 cells), "
+                                      "%d fields of the +-40 mT loop, FP64" % nf,
+                          "value": ib / tb, "unit": "iters/s (summed over samples)",
+                          "iterations": ib, "seconds": tb,
+                          "per_sample_value": iseq / tseq, "per_sample_seconds": tseq,
+                          "speedup_vs_per_sample": (ib / tb) / (iseq / tseq),
+                          "status": [int(rcb), int(rcs)]}
     if not a.no_cpu:
         iters = a.cpu_iters if a.workload == "film" else max(1, a.cpu_iters // 5)
         out["cpu_baseline"] = cpu_baseline(w, iters, field, label)
