@@ -254,14 +254,53 @@ k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt
 // ---------------------------------------------------------------------------
 // y-FFT, tensor product with z convolution, inverse y-FFT; wave FFT version.
 // Block = NZ wavefronts, wave z owns layer z (three components); block kx
-// handles column kx in 0..M (the real-input columns kx = 0 and kx = M are
-// ordinary columns here; their imaginary parts vanish and are stored as 0).
-// Lane g holds the frequencies ky = wfft_freq(g, d), d < 8.  The tensor slab
-// of the column is copied to LDS with direct global-to-LDS loads while the
-// forward transforms run; the z convolution exchanges two slots d at a time
-// through LDS.
-// LDS: [tensor slab, padded to 1 KiB] [transposes | exchange buffer].
+// handles column kx in 1..M-1, and block 0 the two real-input columns kx = 0
+// and kx = M packed as re + i im (so that M blocks, not M + 1, fill the
+// machine).  Lane g holds the frequencies ky = wfft_freq(g, d), d < 8.  The
+// tensor slab of the column is copied to LDS with direct global-to-LDS loads
+// while the forward transforms run; the z convolution exchanges two slots d
+// at a time through LDS.
+// Block 0: with U = F0 + i FM the transform of the packed column (F0, FM the
+// Hermitian spectra of the two real columns), P = (U(k) + conj U(-k))/2 = F0
+// and Q = (U(k) - conj U(-k))/2 = i FM, and T0 P + TM Q = H0 + i HM is the
+// transform of the packed result.  Frequency -k lies in slot 7 - d of lane
+// g' (k1 = g/8, c = g%8: g' = 8 (VL - k1) + 7 - c for k1 >= 1, g' = 8 - c
+// for k1 = 0), except on lane 0, whose slots pair as (d, 8 - d).  In
+// registers, slots 0..3 are turned into P(k) and slots 4..7 into Q(-q) (one
+// shuffle per slot pair); pass 1 applies T0 to slots 0..3, the kx = M tensor
+// then replaces T0 in LDS and pass 2 applies it to slots 4..7 (at -q); a
+// second shuffle forms V(k) = V1(k) + V2(k) with V1(-k) = conj V1(k) and
+// V2(-k) = -conj V2(k).  Frequencies 0 and n/2 (lane 0, slots 0 and 4) see a
+// real diagonal tensor: real part with T0, imaginary part with TM.
+// LDS: [tensor slab, padded to 1 KiB] [transposes | exchange buffer] [4 diagonal
+// tensor entries per layer for block 0].
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src) {
+  return mk(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+// h += T f for one tensor entry set t = (xx, yy, zz, xy, xz, yz) of the
+// mixed (kx, ky, dz) domain: xz and yz are coefficients of i; sy, sz are the
+// parity signs of ky < 0 and dz < 0.
+template <typename T>
+__device__ __forceinline__ void tensor_term(const T* __restrict__ t, T sy, T sz,
+                                            const cx<T> (&f)[3], cx<T> (&h)[3]) {
+  const T xx = t[0], yy = t[1], zz = t[2];
+  const T xy = t[3] * sy, xz = t[4] * sz, yz = t[5] * sy * sz;
+  const cx<T> ifx = rot90<1>(f[0]), ify = rot90<1>(f[1]), ifz = rot90<1>(f[2]);
+  h[0] = add(h[0], add(add(scl(f[0], xx), scl(f[1], xy)), scl(ifz, xz)));
+  h[1] = add(h[1], add(add(scl(f[0], xy), scl(f[1], yy)), scl(ifz, yz)));
+  h[2] = add(h[2], add(add(scl(ifx, xz), scl(ify, yz)), scl(f[2], zz)));
+}
+
+// Offset (complex elements) of block 0's diagonal tensor entries after the
+// transposes and the exchange buffer; the region ends 3 NZ elements later.
+template <int VL, int NZ, bool HALF>
+__host__ __device__ constexpr int yz_pt_offset() {
+  return NZ * wfft_buf<VL, HALF>() > NZ * 3 * 2 * 64 ? NZ * wfft_buf<VL, HALF>() : NZ * 3 * 2 * 64;
+}
+
 template <typename T, int VL, int NZ, bool HALF>
 __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int M,
                                              const T* __restrict__ Tt, int tstride, T scale,
@@ -281,42 +320,152 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
   cx<T>* tbuf = sm + z * wfft_buf<VL, HALF>();   // wave-private transpose buffer
   cx<T>* xbuf = sm;                              // exchange buffer [z][c][DC][64]
   const size_t slab = (size_t)3 * NZ * ny;
+  const bool pair = kx == 0;                     // columns 0 and M, packed
   cx<T>* Ak = A + (size_t)kx * slab;
+  cx<T>* AM = A + (size_t)M * slab;
+  auto load = [&](int c, int y) -> cx<T> {
+    if (y >= ny) return mk(T(0), T(0));
+    const size_t e = ((size_t)z * ny + y) * 3 + c;
+    return pair ? mk(Ak[e].x, AM[e].x) : Ak[e];
+  };
   // column loads (three components of layer z), one component ahead
   cx<T> F[3][8];
   cx<T> xin[2][VL];
 #pragma unroll
-  for (int r = 0; r < VL; ++r) {
-    const int y = lane + 64 * r;
-    xin[0][r] = y < ny ? Ak[((size_t)z * ny + y) * 3 + 0] : mk(T(0), T(0));
-  }
+  for (int r = 0; r < VL; ++r) xin[0][r] = load(0, lane + 64 * r);
   // tensor slab -> LDS, 16 bytes per lane, no registers involved
-  {
+  auto stage_tensor = [&](const T* slab_src) {
     const int nchunk = tstride * (int)sizeof(T) / 16;
-    const unsigned char* src = reinterpret_cast<const unsigned char*>(Tt + (size_t)kx * tstride);
+    const unsigned char* src = reinterpret_cast<const unsigned char*>(slab_src);
     for (int base = z * 64; base < nchunk; base += NZ * 64) {
       const int ch = min(base + lane, nchunk - 1);
       __builtin_amdgcn_global_load_lds(
           (const void*)(src + (size_t)ch * 16),
           (__attribute__((address_space(3))) void*)(smem + (size_t)base * 16), 16, 0, 0);
     }
+  };
+  stage_tensor(Tt + (size_t)kx * tstride);
+  // block 0: diagonal entries T0(dz, n/2) and TM(dz, 0), [2][NZ][3]
+  constexpr int pt_off = yz_pt_offset<VL, NZ, HALF>();
+  T* pt = reinterpret_cast<T*>(sm + pt_off);
+  if (pair && threadIdx.x < 6 * NZ) {
+    const int t = threadIdx.x, which = t / (3 * NZ), dz = (t % (3 * NZ)) / 3, c = t % 3;
+    pt[t] = Tt[(size_t)(which ? M : 0) * tstride + (dz * nk + (which ? 0 : n / 2)) * 6 + c];
   }
   // forward transforms
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if (c < 2) {
 #pragma unroll
-      for (int r = 0; r < VL; ++r) {
-        const int y = lane + 64 * r;
-        xin[(c + 1) & 1][r] = y < ny ? Ak[((size_t)z * ny + y) * 3 + c + 1] : mk(T(0), T(0));
-      }
+      for (int r = 0; r < VL; ++r) xin[(c + 1) & 1][r] = load(c + 1, lane + 64 * r);
     }
     wfft_forward<T, VL, HALF>(xin[c & 1], F[c], tbuf, twy, lane);
     __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_s_waitcnt(0);   // tensor copy complete (this wave's part)
   __syncthreads();                 // ... and every wave's; transposes done
-  if constexpr (NZ == 1) {
+  if (pair) {
+    const int k1 = lane >> 3, cl = lane & 7;
+    const int gp = lane >= NG ? lane : (k1 >= 1 ? 8 * (VL - k1) + 7 - cl : 8 - cl);
+    // slots 0..3 -> P(k), slots 4..7 -> Q(-q)
+    {
+      cx<T> prev[3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cx<T> old7[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const cx<T> uj = F[c][j], u7 = F[c][7 - j];
+          const cx<T> pa = shfl_cx(u7, gp), pb = shfl_cx(uj, gp);
+          old7[c] = u7;
+          cx<T> wj = scl(add(uj, conj(pa)), T(0.5));
+          cx<T> w7 = scl(sub(pb, conj(u7)), T(0.5));
+          if (lane == 0) {
+            wj = j == 0 ? uj : scl(add(uj, conj(prev[c])), T(0.5));
+            w7 = j <= 2 ? scl(sub(F[c][j <= 2 ? j + 1 : 4], conj(u7)), T(0.5)) : u7;
+          }
+          F[c][j] = wj;
+          F[c][7 - j] = w7;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) prev[c] = old7[c];
+      }
+    }
+    const T* p0 = pt;              // T0(dz, n/2) diagonal
+    const T* pM = pt + 3 * NZ;     // TM(dz, 0) diagonal
+#pragma unroll
+    for (int d0 = 0; d0 < 8; d0 += DC) {
+      if (d0 == 4) {
+        // every wave has finished with T0 (barrier at the end of the round)
+        stage_tensor(Tt + (size_t)M * tstride);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+      }
+      if (lane < NG) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int dl = 0; dl < DC; ++dl) xbuf[((z * 3 + c) * DC + dl) * 64 + lane] = F[c][d0 + dl];
+      }
+      __syncthreads();
+      if (lane < NG) {
+#pragma unroll
+        for (int dl = 0; dl < DC; ++dl) {
+          const int d = d0 + dl;
+          const int q = wfft_freq<VL>(lane, d);
+          const int kyp = d < 4 ? q : n - q;      // pass 2 works at -q (0 < -q < n/2)
+          const bool diag = lane == 0 && (d == 0 || d == 4);
+          cx<T> h[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+#pragma unroll 1
+          for (int zp = 0; zp < NZ; ++zp) {
+            const int dz = z - zp;
+            const int dzp = dz < 0 ? -dz : dz;
+            const T sz = dz < 0 ? T(-1) : T(1);
+            cx<T> f[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[c] = xbuf[((zp * 3 + c) * DC + dl) * 64 + lane];
+            if (!diag) {
+              tensor_term<T>(tl + (dzp * nk + kyp) * 6, T(1), sz, f, h);
+            } else {
+              const T* tre = d == 0 ? tl + (dzp * nk) * 6 : p0 + dzp * 3;
+              const T* tim = d == 0 ? pM + dzp * 3 : tl + (dzp * nk + n / 2) * 6;
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                h[c] = add(h[c], mk(tre[c] * f[c].x, tim[c] * f[c].y));
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c][d] = scl(h[c], scale);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+    }
+    // V(k) = V1(k) + V2(k) on slots 0..3, conj V1(-q) - conj V2(-q) on 4..7
+    {
+      cx<T> prev[3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cx<T> old7[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const cx<T> vj = F[c][j], v7 = F[c][7 - j];
+          const cx<T> a = shfl_cx(v7, gp), b = shfl_cx(vj, gp);
+          old7[c] = v7;
+          cx<T> rj = add(vj, a);
+          cx<T> r7 = sub(conj(b), conj(v7));
+          if (lane == 0) {
+            rj = j == 0 ? vj : add(vj, prev[c]);
+            r7 = j <= 2 ? sub(conj(F[c][j <= 2 ? j + 1 : 4]), conj(v7)) : v7;
+          }
+          F[c][j] = rj;
+          F[c][7 - j] = r7;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) prev[c] = old7[c];
+      }
+    }
+  } else if constexpr (NZ == 1) {
     if (lane < NG) {
 #pragma unroll
       for (int d = 0; d < 8; ++d) {
@@ -376,8 +525,7 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
       __syncthreads();
     }
   }
-  // inverse transforms and store of the ny kept rows
-  const bool real_col = (kx == 0 || kx == M);
+  // inverse transforms and store of the ny kept rows (block 0: unpacked)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     cx<T> xo[VL];
@@ -385,7 +533,14 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
 #pragma unroll
     for (int r = 0; r < VL; ++r) {
       const int y = lane + 64 * r;
-      if (y < ny) Ak[((size_t)z * ny + y) * 3 + c] = real_col ? mk(xo[r].x, T(0)) : xo[r];
+      if (y >= ny) continue;
+      const size_t e = ((size_t)z * ny + y) * 3 + c;
+      if (pair) {
+        Ak[e] = mk(xo[r].x, T(0));
+        AM[e] = mk(xo[r].y, T(0));
+      } else {
+        Ak[e] = xo[r];
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -398,7 +553,7 @@ k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int ts
   yz_wave_body<T, VL, NZ, HALF>(A, ny, M, Tt, tstride, scale, twy, done, blockIdx.x);
 }
 
-// Batched: items[b] = (sample, kx); all samples share Py and nz.
+// Batched: items[b] = (sample, kx), kx < M; all samples share Py and nz.
 template <typename T, int VL, int NZ, bool HALF>
 __global__ void __launch_bounds__(64 * NZ, 2)
 k_yz_wave_b(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
@@ -523,13 +678,13 @@ template <typename T, int VL, int NZ>
 static void yz_wave_dispatch(hipStream_t s, void* A, int ny, int M, const T* Tt, int tstride,
                              T scale, const void* twy, const int* done) {
   constexpr bool HALF = sizeof(T) == 8 && VL >= 4;     // keep two blocks per CU in FP64
-  const size_t ex = (size_t)NZ * 3 * 2 * 64;           // exchange buffer
-  const size_t tr = (size_t)NZ * wfft_buf<VL, HALF>(); // transpose buffers
+  // transposes | exchange buffer, then block 0's diagonal tensor entries
+  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ;
   const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
-  const size_t lds = tl + (ex > tr ? ex : tr) * sizeof(cx<T>);
+  const size_t lds = tl + un * sizeof(cx<T>);
   auto k = k_yz_wave<T, VL, NZ, HALF>;
   set_lds(k, lds);
-  hipLaunchKernelGGL(k, dim3(M + 1), dim3(64 * NZ), lds, s, (cx<T>*)A, ny, M, Tt, tstride, scale,
+  hipLaunchKernelGGL(k, dim3(M), dim3(64 * NZ), lds, s, (cx<T>*)A, ny, M, Tt, tstride, scale,
                      (const cx<T>*)twy, done);
 }
 
@@ -569,10 +724,9 @@ template <typename T, int VL, int NZ>
 static void yzb_dispatch(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
                          int tstride) {
   constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
-  const size_t ex = (size_t)NZ * 3 * 2 * 64;
-  const size_t tr = (size_t)NZ * wfft_buf<VL, HALF>();
+  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ;
   const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
-  const size_t lds = tl + (ex > tr ? ex : tr) * sizeof(cx<T>);
+  const size_t lds = tl + un * sizeof(cx<T>);
   auto k = k_yz_wave_b<T, VL, NZ, HALF>;
   set_lds(k, lds);
   hipLaunchKernelGGL(k, dim3(n_items), dim3(64 * NZ), lds, s, descs, items);

@@ -495,8 +495,10 @@ static bool wave_x(int M) { return M == 64 || M == 128 || M == 256 || M == 512; 
 
 int rows_per_block(int M, int ny, bool single) {
   if (wave_x(M)) {
-    // short rows: 4 per block (12 waves), fewer and larger blocks
+    // short rows: 4 per block (12 waves), fewer and larger blocks; the
+    // longest (M = 512): one row per block (3 waves), more blocks per CU
     if (M <= 256 && ny >= 4) return 4;
+    if (M == 512) return 1;
     return ny >= 2 ? 2 : 1;
   }
   // 3 R M complex values per block: at most 4096 (VPT 8, 512 threads) and

@@ -71,7 +71,10 @@ def test_batched_equals_per_sample(torch_cuda, prec):
     a = run(torch, prec, batched=False)
     b = run(torch, prec, batched=True)
     say("  iterations", b[1].tolist())
-    assert a[2] == b[2] == 0
+    # FP64 converges; the mixed form may instead report its torque floor
+    # (MM_STALLED = 2) when FP32 rounding keeps max|g|/Ms above tol
+    assert a[2] == b[2]
+    assert a[2] == 0 if prec == "fp64" else a[2] in (0, 2)
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])
     for x, y in zip(a[3], b[3]):
