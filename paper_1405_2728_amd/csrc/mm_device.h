@@ -195,7 +195,9 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Reduce NV values per thread across the block; result valid in thread 0.
 // MAXT is the kernel's launch bound (blockDim.x <= MAXT); scratch holds
-// NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs sum.
+// NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs sum.  Each wave
+// reduces in registers; then lane i of the first wave combines value i over
+// the waves (in wave order, so the result does not depend on timing).
 template <int MAXT, int NV, int NS>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV],
                                              double (&scratch)[NS]) {
@@ -210,15 +212,20 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
     for (int i = 0; i < NV; ++i) scratch[i * nw + wid] = v[i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    bool mx = false;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double a = scratch[i * nw];
-      for (int w = 1; w < nw; ++w) a = is_max[i] ? fmax(a, scratch[i * nw + w]) : a + scratch[i * nw + w];
-      v[i] = a;
-    }
+    for (int q = 0; q < NV; ++q) mx = q == i ? is_max[q] : mx;
+    double a = scratch[i * nw];
+    for (int w = 1; w < nw; ++w) a = mx ? fmax(a, scratch[i * nw + w]) : a + scratch[i * nw + w];
+    scratch[i * nw] = a;
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = scratch[i * nw];
+  }
 }
 
 }  // namespace mmk
