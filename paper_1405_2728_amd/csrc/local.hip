@@ -42,46 +42,50 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
   }
 }
 
-// Single block: finish the reductions in a fixed order, then (thread 0) the
-// stop rule, the step size of eq. (12) and the iteration counters.
-__global__ void __launch_bounds__(1024) k_finish(const double* __restrict__ partials, int nblocks,
-                                                 MinState* __restrict__ st, double Ms, double V) {
-  __shared__ double scratch[kNPartial * 1024 / 64];
+// One block: reduce the per-block sums in a fixed order (each thread sums
+// rows tid, tid + T, ... with kFinishRows rows in flight), then (thread 0)
+// the stop rule, the step size of eq. (12) and the iteration counters.
+constexpr int kFinishThreads = 256;
+constexpr int kFinishRows = 4;
+
+__device__ __forceinline__ void finish_block(const double* __restrict__ partials, int nb,
+                                             MinState* __restrict__ st, double Ms, double V) {
+  __shared__ double scratch[kNPartial * kFinishThreads / 64];
   if (st->done != 0) return;
   double v[kNPartial] = {};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+  for (int b0 = threadIdx.x; b0 < nb; b0 += kFinishRows * kFinishThreads) {
+    double x[kFinishRows][kNPartial];
 #pragma unroll
-    for (int q = 0; q < kNPartial; ++q) {
-      const double x = partials[(size_t)b * kNPartial + q];
-      v[q] = q == kPartMax ? fmax(v[q], x) : v[q] + x;
+    for (int u = 0; u < kFinishRows; ++u) {
+      const int b = min(b0 + u * kFinishThreads, nb - 1);
+#pragma unroll
+      for (int q = 0; q < kNPartial; ++q) x[u][q] = partials[(size_t)b * kNPartial + q];
+    }
+#pragma unroll
+    for (int u = 0; u < kFinishRows; ++u) {
+      if (b0 + u * kFinishThreads >= nb) break;
+#pragma unroll
+      for (int q = 0; q < kNPartial; ++q)
+        v[q] = q == kPartMax ? fmax(v[q], x[u][q]) : v[q] + x[u][q];
     }
   }
   bool is_max[kNPartial];
   for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
-  block_reduce<1024>(v, is_max, scratch);
+  block_reduce<kFinishThreads>(v, is_max, scratch);
   if (threadIdx.x != 0) return;
   finish_decision(st, v, Ms, V);
 }
 
+__global__ void __launch_bounds__(kFinishThreads) k_finish(const double* __restrict__ partials,
+                                                           int nblocks, MinState* __restrict__ st,
+                                                           double Ms, double V) {
+  finish_block(partials, nblocks, st, Ms, V);
+}
+
 // Batched: block b finishes sample b of the table.
-__global__ void __launch_bounds__(1024) k_finish_b(const BatchDesc* __restrict__ descs) {
-  __shared__ double scratch[kNPartial * 1024 / 64];
+__global__ void __launch_bounds__(kFinishThreads) k_finish_b(const BatchDesc* __restrict__ descs) {
   const BatchDesc& d = descs[blockIdx.x];
-  MinState* st = d.st;
-  if (st->done != 0) return;
-  double v[kNPartial] = {};
-  for (int b = threadIdx.x; b < d.nb3; b += blockDim.x) {
-#pragma unroll
-    for (int q = 0; q < kNPartial; ++q) {
-      const double x = d.partials[(size_t)b * kNPartial + q];
-      v[q] = q == kPartMax ? fmax(v[q], x) : v[q] + x;
-    }
-  }
-  bool is_max[kNPartial];
-  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
-  block_reduce<1024>(v, is_max, scratch);
-  if (threadIdx.x != 0) return;
-  finish_decision(st, v, d.Ms, d.V);
+  finish_block(d.partials, d.nb3, d.st, d.Ms, d.V);
 }
 
 // Apply a pending midpoint update (eq. (7)) to m and store s = m+ - m.
@@ -221,11 +225,11 @@ void launch_local(hipStream_t s, const LocalArgs& a) {
 
 void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
                    double V) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partials, nblocks, st, Ms, V);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, nblocks, st, Ms, V);
 }
 
 void launch_finish_batched(hipStream_t s, const BatchDesc* descs, int n_samples) {
-  hipLaunchKernelGGL(k_finish_b, dim3(n_samples), dim3(1024), 0, s, descs);
+  hipLaunchKernelGGL(k_finish_b, dim3(n_samples), dim3(kFinishThreads), 0, s, descs);
 }
 
 void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
