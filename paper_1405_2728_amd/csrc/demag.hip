@@ -295,7 +295,8 @@ __device__ __forceinline__ void tensor_term(const T* __restrict__ t, T sy, T sz,
 }
 
 // Offset (complex elements) of block 0's diagonal tensor entries after the
-// transposes and the exchange buffer; the region ends 3 NZ elements later.
+// transposes and the exchange buffer; they take 3 NZ elements (6 NZ reals),
+// followed by lane 0's saved values (24 per layer).
 template <int VL, int NZ, bool HALF>
 __host__ __device__ constexpr int yz_pt_offset() {
   return NZ * wfft_buf<VL, HALF>() > NZ * 3 * 2 * 64 ? NZ * wfft_buf<VL, HALF>() : NZ * 3 * 2 * 64;
@@ -364,165 +365,123 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
   }
   __builtin_amdgcn_s_waitcnt(0);   // tensor copy complete (this wave's part)
   __syncthreads();                 // ... and every wave's; transposes done
+  // block 0: lane 0 pairs its own slots (d, 8 - d); its values are kept in
+  // LDS [z][c][8] around the two register transforms
+  const int k1 = lane >> 3, cl = lane & 7;
+  const int gp = lane >= NG ? lane : (k1 >= 1 ? 8 * (VL - k1) + 7 - cl : 8 - cl);
+  cx<T>* l0 = sm + pt_off + 3 * NZ + z * 24;
+  auto keep_lane0 = [&]() {
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) l0[c * 8 + d] = F[c][d];
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
   if (pair) {
-    const int k1 = lane >> 3, cl = lane & 7;
-    const int gp = lane >= NG ? lane : (k1 >= 1 ? 8 * (VL - k1) + 7 - cl : 8 - cl);
     // slots 0..3 -> P(k), slots 4..7 -> Q(-q)
-    {
-      cx<T> prev[3];
+    keep_lane0();
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cx<T> old7[3];
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const cx<T> uj = F[c][j], u7 = F[c][7 - j];
-          const cx<T> pa = shfl_cx(u7, gp), pb = shfl_cx(uj, gp);
-          old7[c] = u7;
-          cx<T> wj = scl(add(uj, conj(pa)), T(0.5));
-          cx<T> w7 = scl(sub(pb, conj(u7)), T(0.5));
-          if (lane == 0) {
-            wj = j == 0 ? uj : scl(add(uj, conj(prev[c])), T(0.5));
-            w7 = j <= 2 ? scl(sub(F[c][j <= 2 ? j + 1 : 4], conj(u7)), T(0.5)) : u7;
-          }
-          F[c][j] = wj;
-          F[c][7 - j] = w7;
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> uj = F[c][j], u7 = F[c][7 - j];
+        const cx<T> pa = shfl_cx(u7, gp), pb = shfl_cx(uj, gp);
+        cx<T> wj = scl(add(uj, conj(pa)), T(0.5));
+        cx<T> w7 = scl(sub(pb, conj(u7)), T(0.5));
+        if (lane == 0) {
+          wj = j == 0 ? uj : scl(add(uj, conj(l0[c * 8 + ((8 - j) & 7)])), T(0.5));
+          w7 = j <= 2 ? scl(sub(l0[c * 8 + j + 1], conj(u7)), T(0.5)) : u7;
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) prev[c] = old7[c];
-      }
-    }
-    const T* p0 = pt;              // T0(dz, n/2) diagonal
-    const T* pM = pt + 3 * NZ;     // TM(dz, 0) diagonal
-#pragma unroll
-    for (int d0 = 0; d0 < 8; d0 += DC) {
-      if (d0 == 4) {
-        // every wave has finished with T0 (barrier at the end of the round)
-        stage_tensor(Tt + (size_t)M * tstride);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-      }
-      if (lane < NG) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int dl = 0; dl < DC; ++dl) xbuf[((z * 3 + c) * DC + dl) * 64 + lane] = F[c][d0 + dl];
-      }
-      __syncthreads();
-      if (lane < NG) {
-#pragma unroll
-        for (int dl = 0; dl < DC; ++dl) {
-          const int d = d0 + dl;
-          const int q = wfft_freq<VL>(lane, d);
-          const int kyp = d < 4 ? q : n - q;      // pass 2 works at -q (0 < -q < n/2)
-          const bool diag = lane == 0 && (d == 0 || d == 4);
-          cx<T> h[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
-#pragma unroll 1
-          for (int zp = 0; zp < NZ; ++zp) {
-            const int dz = z - zp;
-            const int dzp = dz < 0 ? -dz : dz;
-            const T sz = dz < 0 ? T(-1) : T(1);
-            cx<T> f[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) f[c] = xbuf[((zp * 3 + c) * DC + dl) * 64 + lane];
-            if (!diag) {
-              tensor_term<T>(tl + (dzp * nk + kyp) * 6, T(1), sz, f, h);
-            } else {
-              const T* tre = d == 0 ? tl + (dzp * nk) * 6 : p0 + dzp * 3;
-              const T* tim = d == 0 ? pM + dzp * 3 : tl + (dzp * nk + n / 2) * 6;
-#pragma unroll
-              for (int c = 0; c < 3; ++c)
-                h[c] = add(h[c], mk(tre[c] * f[c].x, tim[c] * f[c].y));
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < 3; ++c) F[c][d] = scl(h[c], scale);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-      __syncthreads();
-    }
-    // V(k) = V1(k) + V2(k) on slots 0..3, conj V1(-q) - conj V2(-q) on 4..7
-    {
-      cx<T> prev[3];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cx<T> old7[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const cx<T> vj = F[c][j], v7 = F[c][7 - j];
-          const cx<T> a = shfl_cx(v7, gp), b = shfl_cx(vj, gp);
-          old7[c] = v7;
-          cx<T> rj = add(vj, a);
-          cx<T> r7 = sub(conj(b), conj(v7));
-          if (lane == 0) {
-            rj = j == 0 ? vj : add(vj, prev[c]);
-            r7 = j <= 2 ? sub(conj(F[c][j <= 2 ? j + 1 : 4]), conj(v7)) : v7;
-          }
-          F[c][j] = rj;
-          F[c][7 - j] = r7;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) prev[c] = old7[c];
-      }
-    }
-  } else if constexpr (NZ == 1) {
-    if (lane < NG) {
-#pragma unroll
-      for (int d = 0; d < 8; ++d) {
-        const int ky = wfft_freq<VL>(lane, d);
-        const bool neg = ky > n / 2;
-        const int kyp = neg ? n - ky : ky;
-        const T sy = neg ? T(-1) : T(1);
-        const T* t = tl + kyp * 6;
-        const T xx = t[0], yy = t[1], zz = t[2], xy = t[3] * sy;
-        const cx<T> fx = F[0][d], fy = F[1][d], fz = F[2][d];
-        F[0][d] = scl(add(scl(fx, xx), scl(fy, xy)), scale);
-        F[1][d] = scl(add(scl(fx, xy), scl(fy, yy)), scale);
-        F[2][d] = scl(fz, zz * scale);
+        F[c][j] = wj;
+        F[c][7 - j] = w7;
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-  } else {
+  }
+  // Tensor product.  Block 0: slots 0..3 with the kx = 0 tensor, slots 4..7
+  // (at -q) with the kx = M tensor staged in between; lane 0's slots 0 and 4
+  // (ky = 0, n/2) see real diagonal tensors, real part T0, imaginary part TM.
+  const T* p0 = pt;              // T0(dz, n/2) diagonal
+  const T* pM = pt + 3 * NZ;     // TM(dz, 0) diagonal
+  constexpr int DCP = NZ == 1 ? 1 : DC;   // one layer: no exchange needed
 #pragma unroll
-    for (int d0 = 0; d0 < 8; d0 += DC) {
+  for (int d0 = 0; d0 < 8; d0 += DCP) {
+    if (pair && d0 == 4) {
+      // every wave has finished with T0 (barrier at the end of the round)
+      stage_tensor(Tt + (size_t)M * tstride);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    if constexpr (NZ > 1) {
       if (lane < NG) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int dl = 0; dl < DC; ++dl) xbuf[((z * 3 + c) * DC + dl) * 64 + lane] = F[c][d0 + dl];
+          for (int dl = 0; dl < DCP; ++dl) xbuf[((z * 3 + c) * DCP + dl) * 64 + lane] = F[c][d0 + dl];
       }
       __syncthreads();
-      if (lane < NG) {
+    }
+    if (lane < NG) {
 #pragma unroll
-        for (int dl = 0; dl < DC; ++dl) {
-          const int ky = wfft_freq<VL>(lane, d0 + dl);
-          const bool neg = ky > n / 2;
-          const int kyp = neg ? n - ky : ky;
-          const T sy = neg ? T(-1) : T(1);
-          cx<T> h0 = mk(T(0), T(0)), h1 = h0, h2 = h0;
+      for (int dl = 0; dl < DCP; ++dl) {
+        const int d = d0 + dl;
+        const int q = wfft_freq<VL>(lane, d);
+        const bool neg = q > n / 2;
+        const bool at_minus = pair && d >= 4;
+        const int kyp = (neg || at_minus) ? n - q : q;
+        const T sy = (neg && !at_minus) ? T(-1) : T(1);
+        const bool diag = pair && lane == 0 && (d == 0 || d == 4);
+        cx<T> h[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
 #pragma unroll 1
-          for (int zp = 0; zp < NZ; ++zp) {
-            const int dz = z - zp;
-            const int dzp = dz < 0 ? -dz : dz;
-            const T sz = dz < 0 ? T(-1) : T(1);
-            const T* t = tl + (dzp * nk + kyp) * 6;
-            const T xx = t[0], yy = t[1], zz = t[2];
-            const T xy = t[3] * sy, xz = t[4] * sz, yz = t[5] * sy * sz;
-            const cx<T> fx = xbuf[((zp * 3 + 0) * DC + dl) * 64 + lane];
-            const cx<T> fy = xbuf[((zp * 3 + 1) * DC + dl) * 64 + lane];
-            const cx<T> fz = xbuf[((zp * 3 + 2) * DC + dl) * 64 + lane];
-            const cx<T> ifx = rot90<1>(fx), ify = rot90<1>(fy), ifz = rot90<1>(fz);
-            h0 = add(h0, add(add(scl(fx, xx), scl(fy, xy)), scl(ifz, xz)));
-            h1 = add(h1, add(add(scl(fx, xy), scl(fy, yy)), scl(ifz, yz)));
-            h2 = add(h2, add(add(scl(ifx, xz), scl(ify, yz)), scl(fz, zz)));
+        for (int zp = 0; zp < NZ; ++zp) {
+          const int dz = z - zp;
+          const int dzp = dz < 0 ? -dz : dz;
+          const T sz = dz < 0 ? T(-1) : T(1);
+          cx<T> f[3];
+          if constexpr (NZ > 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[c] = xbuf[((zp * 3 + c) * DCP + dl) * 64 + lane];
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[c] = F[c][d];
           }
-          F[0][d0 + dl] = scl(h0, scale);
-          F[1][d0 + dl] = scl(h1, scale);
-          F[2][d0 + dl] = scl(h2, scale);
-          __builtin_amdgcn_sched_barrier(0);
+          if (!diag) {
+            tensor_term<T>(tl + (dzp * nk + kyp) * 6, sy, sz, f, h);
+          } else {
+            const T* tre = d == 0 ? tl + (dzp * nk) * 6 : p0 + dzp * 3;
+            const T* tim = d == 0 ? pM + dzp * 3 : tl + (dzp * nk + n / 2) * 6;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[c] = add(h[c], mk(tre[c] * f[c].x, tim[c] * f[c].y));
+          }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[c][d] = scl(h[c], scale);
+        __builtin_amdgcn_sched_barrier(0);
       }
-      __syncthreads();
+    }
+    if constexpr (NZ > 1) __syncthreads();
+  }
+  if (pair) {
+    // V(k) = V1(k) + V2(k) on slots 0..3, conj V1(-q) - conj V2(-q) on 4..7
+    keep_lane0();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> vj = F[c][j], v7 = F[c][7 - j];
+        const cx<T> a = shfl_cx(v7, gp), b = shfl_cx(vj, gp);
+        cx<T> rj = add(vj, a);
+        cx<T> r7 = sub(conj(b), conj(v7));
+        if (lane == 0) {
+          rj = j == 0 ? vj : add(vj, l0[c * 8 + ((8 - j) & 7)]);
+          r7 = j <= 2 ? sub(conj(l0[c * 8 + j + 1]), conj(v7)) : v7;
+        }
+        F[c][j] = rj;
+        F[c][7 - j] = r7;
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
   // inverse transforms and store of the ny kept rows (block 0: unpacked)
@@ -679,7 +638,7 @@ static void yz_wave_dispatch(hipStream_t s, void* A, int ny, int M, const T* Tt,
                              T scale, const void* twy, const int* done) {
   constexpr bool HALF = sizeof(T) == 8 && VL >= 4;     // keep two blocks per CU in FP64
   // transposes | exchange buffer, then block 0's diagonal tensor entries
-  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ;
+  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ + 24 * NZ;
   const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
   const size_t lds = tl + un * sizeof(cx<T>);
   auto k = k_yz_wave<T, VL, NZ, HALF>;
@@ -724,7 +683,7 @@ template <typename T, int VL, int NZ>
 static void yzb_dispatch(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
                          int tstride) {
   constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
-  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ;
+  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ + 24 * NZ;
   const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
   const size_t lds = tl + un * sizeof(cx<T>);
   auto k = k_yz_wave_b<T, VL, NZ, HALF>;
