@@ -227,12 +227,21 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
 
 /* Options (numeric): "tau0" (m/A; 0 = 1e-3/Ms), "poll_every" (iterations
  * between host checks of the stop flag, default 32), "stall_iters" (mixed
- * form: iterations without a new torque minimum before MM_STALLED, default
- * 500; 0 disables), "use_graph" (1 = replay iteration batches as a HIP
+ * form without defect correction: iterations without a new torque minimum
+ * before MM_STALLED, default 500; 0 disables), "use_graph" (1 = replay iteration batches as a HIP
  * graph), "demag_path" (0 = automatic: thin-film path for nz <= 4, full 3-D
  * path otherwise; 1 = thin-film path only; 2 = full 3-D path also for
- * nz <= 4; read by mm_set_geometry).  Unknown keys or values give
- * MM_EINVAL. */
+ * nz <= 4; read by mm_set_geometry), "refine" (mixed form, default 1:
+ * defect correction of the minimiser iterations.  Every poll_every
+ * iterations a double-precision reference pass stores mref = m and
+ * hdref = H_d(mref); each iteration then transforms only m - mref in single
+ * precision and adds hdref, so the single-precision error scales with
+ * |m - mref| and vanishes as the minimiser converges.  Applies where the
+ * double-precision kernels handle the grid's demag path (grids whose
+ * single-precision thin-film block does not fit in double precision run
+ * without it); mm_heff, mm_field_terms, mm_energy and the derivative calls
+ * always use the plain single-precision convolution).  Unknown keys or
+ * values give MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 
 /* Counters of one sample since its last mm_set_geometry: total
@@ -257,7 +266,8 @@ int mm_supported(int prec, int nx, int ny, int nz);
  * choice), 3 "update" (mm_minimize_step only), 4 "y3_fwd", 5 "z3",
  * 6 "y3_inv" (full 3-D path: forward y, z transform with tensor product,
  * inverse y), 7 "finish" (reduction of the per-block sums, stop rule, step
- * choice).
+ * choice), 8 "reference" (the whole double-precision reference pass of the
+ * mixed form's defect correction, one record per pass).
  * mm_kernel_bytes(ctx, sample, id, &bytes) gives that kernel's algorithmic
  * bytes per launch in a minimiser iteration (compulsory reads + writes). */
 int mm_profile(mm_ctx* ctx, int mask);

@@ -15,17 +15,18 @@ using namespace mmk;
 
 namespace {
 
-constexpr int kNumKernels = 8;
+constexpr int kNumKernels = 9;
 // xf: pending update + forward x FFT; yz_thin: y FFT, tensor product with the
 // z convolution, inverse y FFT (grids of at most 4 layers); xil: inverse x
 // FFT + local terms + sums + step choice; update: stand-alone update
 // (single-step calls only); y3_fwd, z3, y3_inv: y FFT, z FFT with tensor
 // product and inverse, inverse y FFT (full 3-D path); finish: reduction of
-// the per-block sums, stop rule and step choice
-const char* const kKernelNames[kNumKernels] = {"xf",     "yz_thin", "xil",   "update",
-                                               "y3_fwd", "z3",      "y3_inv", "finish"};
+// the per-block sums, stop rule and step choice; reference: the whole
+// double-precision reference pass of the single-precision form
+const char* const kKernelNames[kNumKernels] = {"xf",     "yz_thin", "xil",    "update",   "y3_fwd",
+                                               "z3",     "y3_inv",  "finish", "reference"};
 enum { KID_XF = 0, KID_YZ = 1, KID_XIL = 2, KID_UPDATE = 3, KID_Y3F = 4, KID_Z3 = 5, KID_Y3I = 6,
-       KID_FINISH = 7 };
+       KID_FINISH = 7, KID_REF = 8 };
 
 // demag path of a geometry
 enum { PATH_NONE = 0, PATH_THIN = 1, PATH_3D = 2 };
@@ -64,8 +65,25 @@ struct Sample {
   CGState* cg_host = nullptr;
   double* scal = nullptr;
   double* scal_host = nullptr;
+  // double-precision reference of the single-precision form (defect
+  // correction): the iteration transforms m - mref in single precision and
+  // adds hdref = H_d(mref), computed in double precision with its own
+  // tensor, spectrum and twiddles every poll_every iterations
+  bool has_ref = false;
+  void* rTt = nullptr;
+  void* rspec = nullptr;
+  void* rtwx = nullptr;
+  void* rtwy = nullptr;
+  void* rtwz = nullptr;
+  void* rB = nullptr;
+  int rtstride = 0, rR3 = 1;
+  double* mref = nullptr;
+  double* hdref = nullptr;
+  long long ref_age = 0;      // iterations since the last reference pass
   int64_t evals_total = 0, iters_total = 0;
 };
+
+constexpr long long kRefStale = 1LL << 60;
 
 struct ProfRec {
   int id;
@@ -85,6 +103,7 @@ struct mm_ctx {
   int use_graph = 0;
   int batched = 1;              // sweeps of several samples share launches
   int path_pref = 0;            // 0 automatic, 1 thin-film, 2 full 3-D
+  int refine = 1;               // single-precision form: defect correction on
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -163,6 +182,15 @@ void free_sample(Sample& s) {
   dfree(s.cAp);
   dfree(s.cg);
   dfree(s.scal);
+  dfree(s.rTt);
+  dfree(s.rspec);
+  dfree(s.rtwx);
+  dfree(s.rtwy);
+  dfree(s.rtwz);
+  dfree(s.rB);
+  dfree(s.mref);
+  dfree(s.hdref);
+  s.has_ref = false;
   if (s.cg_host) (void)hipHostFree(s.cg_host);
   if (s.scal_host) (void)hipHostFree(s.scal_host);
   s.cg_host = nullptr;
@@ -303,6 +331,7 @@ int build_tensor(mm_ctx* c, Sample& s) {
   launch_fft_cols<double>(st, EX, s.Py, (M + 1) * 6 * s.nz, twy64);
   if (single(c)) launch_extract_thin<float>(st, EX, (float*)s.Tt, M, s.nz, s.Py, s.tstride);
   else launch_extract_thin<double>(st, EX, (double*)s.Tt, M, s.nz, s.Py, s.tstride);
+  if (s.rTt) launch_extract_thin<double>(st, EX, (double*)s.rTt, M, s.nz, s.Py, s.rtstride);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   cleanup();
@@ -368,6 +397,7 @@ int build_tensor3d(mm_ctx* c, Sample& s) {
     launch_fft_cols<double>(st, ET, s.Pz, (M + 1) * 6 * s.Py, tw64[2]);      // [kx][c][ky][kz]
     if (single(c)) launch_extract_3d<float>(st, ET, (float*)s.Tt, M, s.Py, s.Pz, s.tstride);
     else launch_extract_3d<double>(st, ET, (double*)s.Tt, M, s.Py, s.Pz, s.tstride);
+    if (s.rTt) launch_extract_3d<double>(st, ET, (double*)s.rTt, M, s.Py, s.Pz, s.rtstride);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
@@ -414,55 +444,120 @@ LocalArgs local_args(const Sample& s, bool unit_A = false, bool zeeman = true) {
   }
   a.partials = s.partials;
   a.Hdyn = nullptr;
+  a.Hd_add = nullptr;
   a.st = nullptr;
   a.done = nullptr;
   return a;
 }
 
-// m is updated in place when o.iterate and an update is pending.
+// Buffers of one convolution: the context's own precision, or the
+// double-precision reference of a single-precision context.
+struct Conv {
+  bool sp;
+  void* Tt;
+  void* spec;
+  void* twx;
+  void* twy;
+  void* twz;
+  void* B;
+  int tstride, R;
+};
+
+Conv conv_main(const mm_ctx* c, const Sample& s) {
+  return {single(c), s.Tt, s.spec, s.twx, s.twy, s.twz, s.B, s.tstride, s.R3};
+}
+
+Conv conv_ref(const Sample& s) {
+  return {false, s.rTt, s.rspec, s.rtwx, s.rtwy, s.rtwz, s.rB, s.rtstride, s.rR3};
+}
+
+bool use_ref(const mm_ctx* c, const Sample& s) { return single(c) && c->refine && s.has_ref; }
+
+// Stall detection guards the plain single-precision form, whose torque has
+// a floor set by the single-precision convolution; with the defect
+// correction (or in double precision) there is no such floor, and BB's
+// non-monotone stretches must not end a run early.
+long long stall_of(const mm_ctx* c, const Sample& s) {
+  return single(c) && !use_ref(c, s) ? c->stall_iters : 0;
+}
+
+// y and z stages of the convolution (between the x passes); each stage is
+// timed under its own id when timed.
+void enqueue_demag_mid(mm_ctx* c, const Sample& s, const Conv& v, const int* done, bool timed) {
+  hipStream_t st = c->stream;
+  const unsigned prof = c->prof;
+  if (!timed) c->prof = 0;
+  if (s.path == PATH_3D) {
+    const double scale = -s.Ms / ((double)s.M * (double)s.Py * (double)s.Pz);
+    {
+      Timer t(c, KID_Y3F);
+      if (v.sp) launch_y3<float>(st, v.spec, v.B, s.nz, s.ny, s.Py, s.M, -1, v.twy, done);
+      else launch_y3<double>(st, v.spec, v.B, s.nz, s.ny, s.Py, s.M, -1, v.twy, done);
+    }
+    {
+      Timer t(c, KID_Z3);
+      if (v.sp)
+        launch_z3<float>(st, v.B, s.nz, s.Py, s.Pz, s.M, (const float*)v.Tt, v.tstride,
+                         (float)scale, v.twz, done);
+      else
+        launch_z3<double>(st, v.B, s.nz, s.Py, s.Pz, s.M, (const double*)v.Tt, v.tstride, scale,
+                          v.twz, done);
+    }
+    {
+      Timer t(c, KID_Y3I);
+      if (v.sp) launch_y3<float>(st, v.spec, v.B, s.nz, s.ny, s.Py, s.M, 1, v.twy, done);
+      else launch_y3<double>(st, v.spec, v.B, s.nz, s.ny, s.Py, s.M, 1, v.twy, done);
+    }
+  } else {
+    Timer t(c, KID_YZ);
+    const double scale = -s.Ms / ((double)s.M * (double)s.Py);
+    if (v.sp)
+      launch_yz_thin<float>(st, v.spec, s.nz, s.ny, s.Py, s.M, (const float*)v.Tt, v.tstride,
+                            (float)scale, v.twy, done);
+    else
+      launch_yz_thin<double>(st, v.spec, s.nz, s.ny, s.Py, s.M, (const double*)v.Tt, v.tstride,
+                             scale, v.twy, done);
+  }
+  c->prof = prof;
+}
+
+// Reference pass of the defect correction: mref = m (no pending update is
+// applied) and hdref = H_d(mref) in double precision.
+void enqueue_reference(mm_ctx* c, Sample& s, const double* m, const MinState* mst) {
+  hipStream_t st = c->stream;
+  const Conv v = conv_ref(s);
+  const int* done = mst ? &mst->done : nullptr;
+  Timer t(c, KID_REF);
+  launch_xf<double>(st, const_cast<double*>(m), nullptr, nullptr, mst, s.nx, s.ny, s.nz, s.Px, v.R,
+                    v.spec, v.twx, nullptr, s.mref);
+  enqueue_demag_mid(c, s, v, done, false);
+  LocalArgs a = local_args(s);
+  a.m = m;
+  a.done = done;
+  launch_xil<double>(st, v.spec, a, s.Px, v.R, s.hdref, nullptr, v.twx);
+  s.ref_age = 0;
+}
+
+// m is updated in place when o.iterate and an update is pending.  A
+// minimiser iteration of a single-precision context with a reference
+// transforms m - mref and adds hdref.
 void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   hipStream_t st = c->stream;
   MinState* mst = o.iterate ? s.st : nullptr;
   const int* done = mst ? &mst->done : o.done;
   double* mm = const_cast<double*>(m);
+  const Conv v = conv_main(c, s);
+  const bool corr = o.iterate && use_ref(c, s);
   {
     Timer t(c, KID_XF);
-    if (single(c))
-      launch_xf<float>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, s.R3, s.spec, s.twx);
+    if (v.sp)
+      launch_xf<float>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, v.R, v.spec, v.twx,
+                       corr ? s.mref : nullptr, nullptr);
     else
-      launch_xf<double>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, s.R3, s.spec, s.twx);
+      launch_xf<double>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, v.R, v.spec, v.twx,
+                        nullptr, nullptr);
   }
-  if (s.path == PATH_3D) {
-    const double scale = -s.Ms / ((double)s.M * (double)s.Py * (double)s.Pz);
-    {
-      Timer t(c, KID_Y3F);
-      if (single(c)) launch_y3<float>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, -1, s.twy, done);
-      else launch_y3<double>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, -1, s.twy, done);
-    }
-    {
-      Timer t(c, KID_Z3);
-      if (single(c))
-        launch_z3<float>(st, s.B, s.nz, s.Py, s.Pz, s.M, (const float*)s.Tt, s.tstride,
-                         (float)scale, s.twz, done);
-      else
-        launch_z3<double>(st, s.B, s.nz, s.Py, s.Pz, s.M, (const double*)s.Tt, s.tstride, scale,
-                          s.twz, done);
-    }
-    {
-      Timer t(c, KID_Y3I);
-      if (single(c)) launch_y3<float>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, 1, s.twy, done);
-      else launch_y3<double>(st, s.spec, s.B, s.nz, s.ny, s.Py, s.M, 1, s.twy, done);
-    }
-  } else {
-    Timer t(c, KID_YZ);
-    const double scale = -s.Ms / ((double)s.M * (double)s.Py);
-    if (single(c))
-      launch_yz_thin<float>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const float*)s.Tt, s.tstride,
-                            (float)scale, s.twy, done);
-    else
-      launch_yz_thin<double>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const double*)s.Tt, s.tstride,
-                             scale, s.twy, done);
-  }
+  enqueue_demag_mid(c, s, v, done, true);
   LocalArgs a = local_args(s, o.unit_A, o.zeeman);
   a.m = m;
   a.g = o.iterate ? s.g : nullptr;
@@ -473,13 +568,14 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   a.st = mst;
   a.done = done;
   a.Hdyn = mst ? mst->H : nullptr;   // the minimiser's field lives in its state
+  a.Hd_add = corr ? s.hdref : nullptr;
   double* part = o.st_fin ? s.partials : nullptr;
   {
     Timer t(c, KID_XIL);
-    if (single(c))
-      launch_xil<float>(st, s.spec, a, s.Px, s.R3, o.Hd, part, s.twx);
+    if (v.sp)
+      launch_xil<float>(st, v.spec, a, s.Px, v.R, o.Hd, part, v.twx);
     else
-      launch_xil<double>(st, s.spec, a, s.Px, s.R3, o.Hd, part, s.twx);
+      launch_xil<double>(st, v.spec, a, s.Px, v.R, o.Hd, part, v.twx);
   }
   if (o.st_fin) {
     Timer t(c, KID_FINISH);
@@ -487,11 +583,15 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   }
 }
 
+// One minimiser iteration; with the defect correction, a reference pass
+// first whenever the reference is poll_every iterations old (or stale).
 void enqueue_iteration(mm_ctx* c, Sample& s, double* m) {
+  if (use_ref(c, s) && s.ref_age >= c->poll_every) enqueue_reference(c, s, m, s.st);
   EvalOut o;
   o.iterate = true;
   o.st_fin = s.st;
   enqueue_eval(c, s, m, o);
+  ++s.ref_age;
 }
 
 double tau0_of(const mm_ctx* c, const Sample& s) { return c->tau0 > 0 ? c->tau0 : 1e-3 / s.Ms; }
@@ -509,18 +609,20 @@ struct BatchPlan {
   std::vector<int> members;               // sample indices, in table order
   std::vector<BatchGroup> xg, yg;
   BatchDesc* descs = nullptr;
+  BatchDesc* descs_ref = nullptr;         // reference pass (defect correction), or NULL
   WorkItem* items = nullptr;
   hipGraphExec_t graph = nullptr;
   ~BatchPlan() {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (descs) (void)hipFree(descs);
+    if (descs_ref) (void)hipFree(descs_ref);
     if (items) (void)hipFree(items);
   }
 };
 
-bool batchable(const Sample& s) {
+bool batchable(const mm_ctx* c, const Sample& s) {
   return s.path == PATH_THIN && (s.M == 64 || s.M == 128 || s.M == 256 || s.M == 512) &&
-         yz_wave_ok(s.nz, s.Py);
+         yz_wave_ok(s.nz, s.Py) && (!single(c) || !c->refine || s.has_ref);
 }
 
 // XCD-aware order: hardware block b takes logical item xcd_remap(b, n), so
@@ -540,7 +642,7 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
   std::vector<BatchDesc> d;
   for (int k = 0; k < (int)c->smp.size(); ++k) {
     Sample& s = c->smp[k];
-    if (!batchable(s)) continue;
+    if (!batchable(c, s)) continue;
     BatchDesc b;
     const LocalArgs a = local_args(s);
     b.m = m[k];
@@ -570,10 +672,30 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
     b.scale = -s.Ms / ((double)s.M * (double)s.Py);
     b.Ms = s.Ms;
     b.V = s.V;
+    const bool corr = use_ref(c, s);
+    b.mref = corr ? s.mref : nullptr;
+    b.hdref = corr ? s.hdref : nullptr;
+    b.pass = corr ? 1 : 0;
     P.members.push_back(k);
     d.push_back(b);
   }
   if (d.empty()) return MM_OK;
+  // the reference pass: the same blocks on the double-precision buffers
+  const bool refine = single(c) && c->refine;
+  std::vector<BatchDesc> dr;
+  if (refine) {
+    for (int i = 0; i < (int)d.size(); ++i) {
+      const Sample& s = c->smp[P.members[i]];
+      BatchDesc b = d[i];
+      b.spec = s.rspec;
+      b.Tt = s.rTt;
+      b.twx = s.rtwx;
+      b.twy = s.rtwy;
+      b.tstride = s.rtstride;
+      b.pass = 2;
+      dr.push_back(b);
+    }
+  }
   std::vector<WorkItem> all;
   auto add_groups = [&](bool x, std::vector<BatchGroup>& groups) {
     std::vector<BatchGroup> keys;
@@ -604,16 +726,34 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
   add_groups(true, P.xg);
   add_groups(false, P.yg);
   if (hipMalloc((void**)&P.descs, d.size() * sizeof(BatchDesc)) != hipSuccess ||
+      (refine && hipMalloc((void**)&P.descs_ref, d.size() * sizeof(BatchDesc)) != hipSuccess) ||
       hipMalloc((void**)&P.items, all.size() * sizeof(WorkItem)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, MM_ENOMEM, "device allocation for the batch tables failed");
   }
   HIPCHK(c, hipMemcpyAsync(P.descs, d.data(), d.size() * sizeof(BatchDesc), hipMemcpyHostToDevice,
                            c->stream));
+  if (refine)
+    HIPCHK(c, hipMemcpyAsync(P.descs_ref, dr.data(), dr.size() * sizeof(BatchDesc),
+                             hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(P.items, all.data(), all.size() * sizeof(WorkItem),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return MM_OK;
+}
+
+// Reference pass of every batched sample (double precision, same blocks).
+void enqueue_batched_reference(mm_ctx* c, const BatchPlan& P) {
+  if (!P.descs_ref) return;
+  hipStream_t st = c->stream;
+  Timer t(c, KID_REF);
+  for (const auto& g : P.xg)
+    launch_x_batched<double>(st, false, P.descs_ref, P.items + g.off, g.n, g.a, g.b);
+  for (const auto& g : P.yg)
+    launch_yz_batched<double>(st, P.descs_ref, P.items + g.off, g.n, g.a, g.b,
+                              thin_tensor_stride(g.b, g.a, false));
+  for (const auto& g : P.xg)
+    launch_x_batched<double>(st, true, P.descs_ref, P.items + g.off, g.n, g.a, g.b);
 }
 
 // One iteration of every batched sample.
@@ -665,7 +805,8 @@ int read_state(mm_ctx* c, Sample& s) {
 
 int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
   launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                     single(c) ? c->stall_iters : 0, 0, s.H);
+                     stall_of(c, s), 0, s.H);
+  s.ref_age = kRefStale;
   // a run evaluates at most max_iter + 1 times: enqueue no iteration beyond
   // that (such launches would only read the stop flag and return)
   long long left = (long long)max_iter + 1;
@@ -834,6 +975,29 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
             hipMalloc((void**)&s.dev3, 3 * sizeof(double)) == hipSuccess &&
             hipHostMalloc((void**)&s.st_host, sizeof(MinState), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&s.host3, 3 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  // double-precision reference of the single-precision form, where the
+  // double-precision kernels handle the same path for this grid
+  if (ok && sp && choose_path(MM_FP64, c->path_pref, nx, ny, nz) == path) {
+    s.rR3 = rows_per_block(s.M, ny, false);
+    s.rtstride = full ? tensor3_row(s.Pz, false) : thin_tensor_stride(nz, s.Py, false);
+    const size_t nTr = (size_t)(s.M + 1) * (full ? (size_t)(s.Py / 2 + 1) : 1) * s.rtstride;
+    ok = hipMalloc(&s.rTt, nTr * sizeof(double)) == hipSuccess &&
+         hipMalloc(&s.rspec, nspec * 2 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&s.rtwx, (size_t)s.Px * 2 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&s.rtwy, (size_t)s.Py * 2 * sizeof(double)) == hipSuccess &&
+         (!full || hipMalloc(&s.rB, nB * 2 * sizeof(double)) == hipSuccess) &&
+         (!full || hipMalloc(&s.rtwz, (size_t)s.Pz * 2 * sizeof(double)) == hipSuccess) &&
+         hipMalloc((void**)&s.mref, 3ull * s.N * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&s.hdref, 3ull * s.N * sizeof(double)) == hipSuccess;
+    if (ok) {
+      s.has_ref = true;
+      HIPCHK(c, hipMemsetAsync(s.rTt, 0, nTr * sizeof(double), c->stream));
+      launch_twiddles(c->stream, s.rtwx, s.Px, false);
+      launch_twiddles(c->stream, s.rtwy, s.Py, false);
+      if (full) launch_twiddles(c->stream, s.rtwz, s.Pz, false);
+    }
+  }
+  s.ref_age = kRefStale;
   if (!ok) {
     free_sample(s);
     (void)hipGetLastError();
@@ -887,6 +1051,7 @@ int mm_set_material(mm_ctx* c, int sample, double Ms, double A, double Ku, const
     dfree(s.ku_map);
   }
   s.has_mat = true;
+  s.ref_age = kRefStale;   // the reference field scales with Ms
   launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
@@ -1045,9 +1210,10 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     Sample& s = c->smp[k];
     for (int q = 0; q < 3; ++q) s.H[q] = H[((size_t)k * n_fields) * 3 + q];
     launch_reset_state(st, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                       single(c) ? c->stall_iters : 0, 0, s.H);
+                       stall_of(c, s), 0, s.H);
     launch_sweep_start(st, s.st, fields + (size_t)k * n_fields * 3, n_fields,
                        mavg + (size_t)k * n_fields * 3, its + (size_t)k * n_fields, 1.0 / s.N);
+    s.ref_age = kRefStale;
   }
   BatchPlan plan;
   std::vector<char> in_batch(S, 0);
@@ -1075,6 +1241,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
           hipGraph_t g = nullptr;
           hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
           if (e == hipSuccess) {
+            enqueue_batched_reference(c, plan);
             for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
             e = hipStreamEndCapture(c->stream, &g);
           }
@@ -1087,6 +1254,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
         }
         HIPCHK(c, hipGraphLaunch(plan.graph, c->stream));
       } else {
+        enqueue_batched_reference(c, plan);
         for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
       }
     }
@@ -1149,6 +1317,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->use_graph = value != 0.0;
   } else if (!std::strcmp(key, "batched")) {
     c->batched = value != 0.0;
+  } else if (!std::strcmp(key, "refine")) {
+    c->refine = value != 0.0;
   } else if (!std::strcmp(key, "demag_path")) {
     if (value != 0 && value != 1 && value != 2) return fail(c, MM_EINVAL, "demag_path is 0, 1 or 2");
     c->path_pref = (int)value;
@@ -1204,11 +1374,19 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
   const double bsp = s.path == PATH_3D ? (double)(s.M + 1) * s.Py * 3 * s.nz * 2 * sr : 0.0;
   const double ku = s.ku_map ? s.N * 8.0 : 0.0;
   const bool thin = s.path == PATH_THIN;
+  const double corr = use_ref(c, s) ? N3 : 0.0;   // mref in (xf), hdref in (xil)
+  // reference pass (double precision): xf m in, mref and spectrum out; y/z
+  // stages; xil spectrum and m in, hdref out
+  const double spec64 = (double)(s.M + 1) * 3 * s.nz * s.ny * 16.0;
+  const double tens64 = (double)(s.M + 1) * trows * s.rtstride * 8.0;
+  const double bsp64 = s.path == PATH_3D ? (double)(s.M + 1) * s.Py * 3 * s.nz * 16.0 : 0.0;
+  const double mid64 = thin ? 2 * spec64 + tens64 : 2 * spec64 + 4 * bsp64 + tens64;
   double b = 0;
   switch (id) {
-    case KID_XF: b = 4 * N3 + spec; break;          // m, g in; m, s out; spectrum out
+    case KID_XF: b = 4 * N3 + spec + corr; break;   // m, g in; m, s out; spectrum out
     case KID_YZ: b = thin ? 2 * spec + tens : 0; break;   // spectrum in/out; tensor in
-    case KID_XIL: b = spec + 4 * N3 + ku; break;    // spectrum, m, g, s in; g out
+    case KID_XIL: b = spec + 4 * N3 + ku + corr; break;   // spectrum, m, g, s in; g out
+    case KID_REF: b = s.has_ref ? 4 * N3 + 2 * spec64 + mid64 + ku : 0; break;
     case KID_UPDATE: b = 4 * N3; break;             // m, g in; m, s out
     case KID_Y3F: b = thin ? 0 : spec + bsp; break; // spectrum in, y spectrum out
     case KID_Z3: b = thin ? 0 : 2 * bsp + tens; break;    // y spectrum in/out; tensor in

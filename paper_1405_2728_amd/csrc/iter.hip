@@ -13,6 +13,9 @@
 //          extra launch.)
 // Block b works on rows (z, y0 .. y0+R-1) with the XCD-contiguous mapping
 // of xcd_remap so that neighbouring row groups share L2.
+// Defect correction (single-precision form): k_xf may transform m - mref
+// instead of m, and k_xil then adds the double-precision field of mref; a
+// reference pass (double precision) copies m to mref without updating it.
 #include "mm_iter.h"
 #include "mm_wfft.h"
 
@@ -25,12 +28,13 @@ template <typename T, int VPT>
 __global__ void __launch_bounds__(kXsThreads)
 k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
      const MinState* __restrict__ st, int nx, int ny, int nz, int Px, int R,
-     cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
+     cx<T>* __restrict__ out, const cx<T>* __restrict__ twx, const double* __restrict__ msub,
+     double* __restrict__ mcopy) {
   bool upd = false;
   double tau = 0.0;
   if (st != nullptr) {
     if (st->done != 0) return;
-    upd = st->pending != 0;
+    upd = st->pending != 0 && mcopy == nullptr;
     tau = st->last_tau;
   }
   extern __shared__ __align__(16) unsigned char smem[];
@@ -68,6 +72,14 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
             sbuf[(size_t)c * N + i] = mo[c] - mi[c];
             mi[c] = mo[c];
           }
+        }
+        if (mcopy != nullptr) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mcopy[(size_t)c * N + i] = mi[c];
+        }
+        if (msub != nullptr) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mi[c] -= msub[(size_t)c * N + i];
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -146,6 +158,7 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
     for (int c = 0; c < 3; ++c) {
       const cx<T> v = buf[(c * R + r) * M + (x >> 1)];
       hd[c] = (double)((x & 1) ? v.y : v.x);
+      if (a.Hd_add != nullptr) hd[c] += a.Hd_add[(size_t)c * N + i];
     }
     if (Hd_out != nullptr) {
 #pragma unroll
@@ -182,7 +195,9 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
                                           double* __restrict__ sbuf,
                                           const MinState* __restrict__ st, int nx, int ny, int nz,
                                           int R, cx<T>* __restrict__ out,
-                                          const cx<T>* __restrict__ twx, int L) {
+                                          const cx<T>* __restrict__ twx, int L,
+                                          const double* __restrict__ msub,
+                                          double* __restrict__ mcopy) {
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
@@ -190,7 +205,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
   double tau = 0.0;
   if (st != nullptr) {
     if (st->done != 0) return;
-    upd = st->pending != 0;
+    upd = st->pending != 0 && mcopy == nullptr;
     tau = st->last_tau;
   }
   extern __shared__ __align__(16) unsigned char smem[];
@@ -235,6 +250,14 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
             sbuf[(size_t)c * N + i] = mo[c] - mi[u][c];
             mi[u][c] = mo[c];
           }
+        }
+        if (mcopy != nullptr) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mcopy[(size_t)c * N + i] = mi[u][c];
+        }
+        if (msub != nullptr) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mi[u][c] -= msub[(size_t)c * N + i];
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -300,8 +323,10 @@ template <typename T, int VL>
 __global__ void __launch_bounds__(kXwThreads)
 k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
        const MinState* __restrict__ st, int nx, int ny, int nz, int R,
-       cx<T>* __restrict__ out, const cx<T>* __restrict__ twx) {
-  xf_w_body<T, VL>(m, g, sbuf, st, nx, ny, nz, R, out, twx, xcd_remap(blockIdx.x, gridDim.x));
+       cx<T>* __restrict__ out, const cx<T>* __restrict__ twx, const double* __restrict__ msub,
+       double* __restrict__ mcopy) {
+  xf_w_body<T, VL>(m, g, sbuf, st, nx, ny, nz, R, out, twx, xcd_remap(blockIdx.x, gridDim.x),
+                   msub, mcopy);
 }
 
 // Body of the inverse x pass with the local terms for logical block L.
@@ -404,6 +429,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
         for (int cc = 0; cc < 3; ++cc) {
           const cx<T> v = sm[(size_t)(rr * 3 + cc) * RG + wx_pad(x >> 1)];
           hd[cc] = (double)((x & 1) ? v.y : v.x);
+          if (a.Hd_add != nullptr) hd[cc] += a.Hd_add[(size_t)cc * N + i];
         }
         if (Hd_out != nullptr) {
 #pragma unroll
@@ -438,7 +464,8 @@ k_xf_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items)
   const WorkItem it = items[blockIdx.x];
   const BatchDesc& d = descs[it.sample];
   xf_w_body<T, VL>(d.m, d.g, d.s, d.st, d.nx, d.ny, d.nz, d.R, (cx<T>*)d.spec,
-                   (const cx<T>*)d.twx, it.block);
+                   (const cx<T>*)d.twx, it.block, d.pass == 1 ? d.mref : nullptr,
+                   d.pass == 2 ? d.mref : nullptr);
 }
 
 template <typename T, int VL>
@@ -468,9 +495,19 @@ k_xil_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items
     a.H[c] = 0.0;
   }
   a.Hdyn = d.st->H;
+  a.Hd_add = d.pass == 1 ? d.hdref : nullptr;
   a.partials = d.partials;
   a.st = d.st;
   a.done = &d.st->done;
+  if (d.pass == 2) {
+    // reference pass: the demag field of mref only
+    a.g = nullptr;
+    a.s = nullptr;
+    a.st = nullptr;
+    xil_w_body<T, VL>((const cx<T>*)d.spec, a, d.R, d.hdref, nullptr, (const cx<T>*)d.twx,
+                      it.block);
+    return;
+  }
   xil_w_body<T, VL>((const cx<T>*)d.spec, a, d.R, nullptr, d.partials, (const cx<T>*)d.twx,
                     it.block);
 }
@@ -514,13 +551,14 @@ int rows_per_block(int M, int ny, bool single) {
 
 template <typename T, int VL>
 static void xf_wave(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st,
-                    int nx, int ny, int nz, int R, void* out, const void* twx) {
+                    int nx, int ny, int nz, int R, void* out, const void* twx, const double* msub,
+                    double* mcopy) {
   const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
   const int nb = nz * ((ny + R - 1) / R);
   auto k = k_xf_w<T, VL>;
   set_lds(k, lds);
   hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, m, g, sbuf, st, nx, ny, nz, R,
-                     (cx<T>*)out, (const cx<T>*)twx);
+                     (cx<T>*)out, (const cx<T>*)twx, msub, mcopy);
 }
 
 template <typename T, int VL>
@@ -536,13 +574,14 @@ static void xil_wave(hipStream_t s, const void* in, const LocalArgs& a, int R, d
 
 template <typename T>
 void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
-               int ny, int nz, int Px, int R, void* out, const void* twx) {
+               int ny, int nz, int Px, int R, void* out, const void* twx, const double* msub,
+               double* mcopy) {
   const int M = Px / 2;
   switch (M) {
-    case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
-    case 128: xf_wave<T, 2>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
-    case 256: xf_wave<T, 4>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
-    case 512: xf_wave<T, 8>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx); return;
+    case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 128: xf_wave<T, 2>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 256: xf_wave<T, 4>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 512: xf_wave<T, 8>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
     default: break;
   }
   const long long vals = 3LL * R * M;
@@ -552,12 +591,12 @@ void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const Mi
     auto k = k_xf<T, 8>;
     set_lds(k, lds);
     hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 8)), lds, s, m, g, sbuf, st, nx, ny, nz,
-                       Px, R, (cx<T>*)out, (const cx<T>*)twx);
+                       Px, R, (cx<T>*)out, (const cx<T>*)twx, msub, mcopy);
   } else {
     auto k = k_xf<T, 16>;
     set_lds(k, lds);
     hipLaunchKernelGGL(k, dim3(nb), dim3(threads_for(vals, 16)), lds, s, m, g, sbuf, st, nx, ny,
-                       nz, Px, R, (cx<T>*)out, (const cx<T>*)twx);
+                       nz, Px, R, (cx<T>*)out, (const cx<T>*)twx, msub, mcopy);
   }
 }
 
@@ -619,9 +658,9 @@ template void launch_x_batched<double>(hipStream_t, bool, const BatchDesc*, cons
 template void launch_x_batched<float>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
                                       int, int);
 template void launch_xf<double>(hipStream_t, double*, const double*, double*, const MinState*, int,
-                                int, int, int, int, void*, const void*);
+                                int, int, int, int, void*, const void*, const double*, double*);
 template void launch_xf<float>(hipStream_t, double*, const double*, double*, const MinState*, int,
-                               int, int, int, int, void*, const void*);
+                               int, int, int, int, void*, const void*, const double*, double*);
 template void launch_xil<double>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
                                  double*, const void*);
 template void launch_xil<float>(hipStream_t, const void*, const LocalArgs&, int, int, double*,

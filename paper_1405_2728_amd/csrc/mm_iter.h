@@ -9,12 +9,13 @@
 
 namespace mmk {
 
-// Inputs of the local terms of one cell, fetched ahead of use so that a
-// thread can keep several cells' loads in flight.  A missing neighbour
-// (free boundary) is replaced by the cell itself, which contributes zero.
+// Inputs of the local terms of one cell.  A missing neighbour (free
+// boundary) is replaced by the cell itself, which contributes zero; the
+// exchange field is formed as soon as the neighbours arrive, so that only
+// it (not the six neighbours) stays live.
 struct CellIn {
   double m[3];
-  double nb[6][3];   // x-1, x+1, y-1, y+1, z-1, z+1
+  double hex[3];     // exchange field
   double g[3], s[3];
   double ku;
 };
@@ -31,9 +32,13 @@ __device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, C
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double* mc = a.m + (size_t)c * N;
-    d.m[c] = mc[i];
+    const double m0 = mc[i];
+    double nb[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) d.nb[q][c] = mc[j[q]];
+    for (int q = 0; q < 6; ++q) nb[q] = mc[j[q]];
+    d.m[c] = m0;
+    d.hex[c] = a.cx * ((nb[0] - m0) + (nb[1] - m0)) + a.cy * ((nb[2] - m0) + (nb[3] - m0)) +
+               a.cz * ((nb[4] - m0) + (nb[5] - m0));
   }
   if (a.g != nullptr) {
 #pragma unroll
@@ -51,14 +56,7 @@ __device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, C
 __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const double hd[3],
                                              bool bb, const CellIn& d, double part[kNPartial]) {
   const int N = a.nx * a.ny * a.nz;
-  double hex[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double mc = d.m[c];
-    hex[c] = a.cx * ((d.nb[0][c] - mc) + (d.nb[1][c] - mc)) +
-             a.cy * ((d.nb[2][c] - mc) + (d.nb[3][c] - mc)) +
-             a.cz * ((d.nb[4][c] - mc) + (d.nb[5][c] - mc));
-  }
+  const double* hex = d.hex;
   const double* mi = d.m;
   const double mu = mi[0] * a.u[0] + mi[1] * a.u[1] + mi[2] * a.u[2];
   const double pan = a.kan * d.ku * mu;

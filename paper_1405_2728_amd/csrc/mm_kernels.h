@@ -74,6 +74,12 @@ struct BatchDesc {
   double u[3];
   double scale;          // -Ms/(M Py)
   double Ms, V;
+  // defect correction of the single-precision form: pass 0 plain; pass 1
+  // transforms m - mref and adds hdref to the demag field; pass 2 (the
+  // double-precision reference) copies m to mref and writes hdref = H_d(mref)
+  double* mref;
+  double* hdref;
+  int pass;
 };
 // A block of a batched launch: sample index and logical block of its pass.
 struct WorkItem {
@@ -166,6 +172,7 @@ struct LocalArgs {
   double ku, kan;       // scalar Ku; 2/(mu0 Ms)
   double u[3], H[3];
   const double* Hdyn;   // device field overriding H (NULL: use H)
+  const double* Hd_add; // field added to the transformed demag field (NULL: none)
   double* partials;     // [nblocks][kNPartial]
   const MinState* st;   // NULL outside the minimiser
   const int* done;      // NULL outside the minimiser
@@ -189,9 +196,12 @@ void launch_set_mode(hipStream_t s, MinState* st, int mode);
 void launch_clear_pending(hipStream_t s, MinState* st);
 // fused x passes of the thin-film iteration
 int rows_per_block(int M, int ny, bool single);
+// msub (NULL: none) is subtracted from m before the transform; mcopy (NULL:
+// none) receives a copy of m, and then no pending update is applied
 template <typename T>
 void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
-               int ny, int nz, int Px, int R, void* out, const void* twx);
+               int ny, int nz, int Px, int R, void* out, const void* twx, const double* msub,
+               double* mcopy);
 template <typename T>
 // partials: per-block sums out (NULL: none), reduced by launch_finish
 void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,

@@ -196,6 +196,33 @@ def test_minimize_to_tol_cross_stationary(torch_cuda):
     ctx.close()
 
 
+@pytest.mark.parametrize("shape", [(64, 32, 2), (20, 10, 1), (12, 10, 6)])
+def test_mixed_defect_correction_reaches_fp64_tolerance(torch_cuda, shape):
+    """The single-precision form with its defect correction converges to a
+    tolerance far below the plain FP32 convolution's error (1e-9 of Ms) on
+    the thin wave path, the LDS x path and the 3-D path: the oracle's FP64
+    torque at the final state confirms it, and the state is the FP64 run's."""
+    torch = torch_cuda
+    nx, ny, nz = shape
+    d = (5e-9,) * 3
+    say("case mixed defect correction", shape)
+    rng = np.random.default_rng(41)
+    m0 = synth.uniform_with_noise(synth.tilted(30.0), nx, ny, nz, 0.3, rng)
+    out = {}
+    for prec in ("mixed", "fp64"):
+        ctx, P = make(torch, prec, nx, ny, nz, d, H=(-2e3, 1e3, 0))
+        m = torch.tensor(m0, device="cuda")
+        r = ctx.minimize_to_tol(0, m, tol=1e-9, max_iter=200000)
+        out[prec] = (r, m.cpu().numpy())
+        ctx.close()
+    r, mg = out["mixed"]
+    T = om.torque(mg, P.heff(mg), P.Ms)
+    say("  mixed iters", r["iters"], "fp64 iters", out["fp64"][0]["iters"], "oracle torque", T)
+    assert r["converged"] and out["fp64"][0]["converged"]
+    assert T < 1e-9 * 1.01
+    assert np.max(np.abs(mg - out["fp64"][1])) < 1e-5
+
+
 def test_workload0_sweep_matches_oracle(torch_cuda):
     """32x16x1 film, random start, H = 0, 4, ..., 20 mT at 1 degree."""
     torch = torch_cuda

@@ -70,7 +70,8 @@ def test_status_strings(lib):
     while lib.mm_kernel_name(k) is not None:
         names.append(lib.mm_kernel_name(k).decode())
         k += 1
-    assert names == ["xf", "yz_thin", "xil", "update", "y3_fwd", "z3", "y3_inv", "finish"]
+    assert names == ["xf", "yz_thin", "xil", "update", "y3_fwd", "z3", "y3_inv", "finish",
+                     "reference"]
 
 
 def test_argument_validation_without_gpu(lib):
@@ -95,6 +96,8 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"demag_path", 3.0) == -1
         assert lib.mm_set_option(h, b"demag_path", 2.0) == 0
         assert lib.mm_set_option(h, b"demag_path", 0.0) == 0
+        assert lib.mm_set_option(h, b"refine", 0.0) == 0
+        assert lib.mm_set_option(h, b"refine", 1.0) == 0
     finally:
         lib.mm_destroy(h)
     lib.mm_destroy(None)
