@@ -240,9 +240,21 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * double-precision kernels handle the grid's demag path (grids whose
  * single-precision thin-film block does not fit in double precision run
  * without it); mm_heff, mm_field_terms, mm_energy and the derivative calls
- * always use the plain single-precision convolution).  Unknown keys or
- * values give MM_EINVAL. */
+ * always use the plain single-precision convolution), "autotune" (1: the
+ * tile autotuner of the batched form's passes.  mm_set_geometry times the
+ * fused x passes (xf + xil) for every valid number of rows per block on
+ * the sample's own buffers and keeps the fastest; choices are cached per
+ * precision, grid and demag path for the life of the process; default 0
+ * uses a fixed heuristic, so that results do not depend on timing),
+ * "rows_per_block" (0 = automatic; otherwise that tile for every later
+ * mm_set_geometry, which fails with MM_EINVAL where it is not valid: for
+ * testing every tile).  Unknown keys or values give MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
+
+/* Rows per block of the sample's fused x passes (host int output), as the
+ * heuristic, the autotuner or the rows_per_block option chose it at
+ * mm_set_geometry. */
+int mm_rows_per_block(mm_ctx* ctx, int sample, int* rows);
 
 /* Counters of one sample since its last mm_set_geometry: total
  * effective-field evaluations and updates (host int64_t outputs). */

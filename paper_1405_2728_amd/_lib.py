@@ -55,6 +55,7 @@ SIGNATURES = {
                                   C.POINTER(C.c_double)]),
     "mm_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
     "mm_counters": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "mm_rows_per_block": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "mm_supported": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "mm_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "mm_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),

@@ -240,6 +240,11 @@ class Context:
         self._check(self._lib.mm_counters(self._h, sample, C.byref(e), C.byref(i)))
         return e.value, i.value
 
+    def rows_per_block(self, sample):
+        r = C.c_int()
+        self._check(self._lib.mm_rows_per_block(self._h, sample, C.byref(r)))
+        return r.value
+
     # -- timing ---------------------------------------------------------------
     def profile(self, kernels=None):
         """Time the named kernels (None or [] stops; "all" times every

@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mm.h"
@@ -104,6 +107,8 @@ struct mm_ctx {
   int batched = 1;              // sweeps of several samples share launches
   int path_pref = 0;            // 0 automatic, 1 thin-film, 2 full 3-D
   int refine = 1;               // single-precision form: defect correction on
+  int autotune = 0;             // 1: time the x-pass tiles at mm_set_geometry
+  int rows_forced = 0;          // > 0: rows per block of the x passes (tests)
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -787,6 +792,106 @@ void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
   }
 }
 
+// ---- tile autotuner: rows per block of the fused x passes -----------------
+// The x passes (xf, xil) work on R rows per block.  With the autotune
+// option, mm_set_geometry times every valid R on the sample's own buffers
+// (both passes, no update, outputs discarded) and keeps the fastest; the
+// choice is cached per (precision, grid, path) for the process.
+struct TuneKey {
+  int sp, nx, ny, nz, path;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(sp, nx, ny, nz, path) < std::tie(o.sp, o.nx, o.ny, o.nz, o.path);
+  }
+};
+
+std::map<TuneKey, int>& tune_cache() {
+  static std::map<TuneKey, int> m;
+  return m;
+}
+
+std::mutex& tune_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
+// Valid tiles: the wave passes take 192 R threads (R <= 4); the LDS passes
+// up to the heuristic's bound (LDS and threads per block); never above ny.
+std::vector<int> row_tiles(int M, int ny, bool sp) {
+  const bool wave = M == 64 || M == 128 || M == 256 || M == 512;
+  const int hi = wave ? 4 : rows_per_block(M, ny, sp);
+  std::vector<int> v;
+  for (int r = 1; r <= hi && r <= ny; ++r)
+    if (wave || (r & (r - 1)) == 0 || r == hi) v.push_back(r);
+  return v;
+}
+
+// Mean time of one xf + xil pair with R rows per block (microseconds).
+int time_rows(mm_ctx* c, Sample& s, int R, double* us) {
+  hipStream_t st = c->stream;
+  const bool sp = single(c);
+  LocalArgs a = local_args(s);
+  a.m = s.g;   // zeros; no update is applied (no state), nothing is written
+  auto pass = [&]() {
+    if (sp) {
+      launch_xf<float>(st, s.g, nullptr, nullptr, nullptr, s.nx, s.ny, s.nz, s.Px, R, s.spec, s.twx,
+                       nullptr, nullptr);
+      launch_xil<float>(st, s.spec, a, s.Px, R, nullptr, nullptr, s.twx);
+    } else {
+      launch_xf<double>(st, s.g, nullptr, nullptr, nullptr, s.nx, s.ny, s.nz, s.Px, R, s.spec,
+                        s.twx, nullptr, nullptr);
+      launch_xil<double>(st, s.spec, a, s.Px, R, nullptr, nullptr, s.twx);
+    }
+  };
+  constexpr int kReps = 5;
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  pass();
+  pass();
+  HIPCHK(c, hipEventRecord(e0, st));
+  for (int q = 0; q < kReps; ++q) pass();
+  HIPCHK(c, hipEventRecord(e1, st));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  c->ev_pool.push_back(e0);
+  c->ev_pool.push_back(e1);
+  *us = 1e3 * ms / kReps;
+  return MM_OK;
+}
+
+int choose_rows(mm_ctx* c, Sample& s) {
+  const bool sp = single(c);
+  const std::vector<int> tiles = row_tiles(s.M, s.ny, sp);
+  int R = rows_per_block(s.M, s.ny, sp);
+  if (c->rows_forced > 0) {
+    bool ok = false;
+    for (int r : tiles) ok = ok || r == c->rows_forced;
+    if (!ok) return fail(c, MM_EINVAL, "rows_per_block is not a valid tile for this grid");
+    R = c->rows_forced;
+  } else if (c->autotune && tiles.size() > 1) {
+    const TuneKey key{sp ? 1 : 0, s.nx, s.ny, s.nz, s.path};
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      R = it->second;
+    } else {
+      double best = 0.0;
+      for (int r : tiles) {
+        double us = 0.0;
+        int rc = time_rows(c, s, r, &us);
+        if (rc != MM_OK) return rc;
+        if (best == 0.0 || us < best) {
+          best = us;
+          R = r;
+        }
+      }
+      tune_cache()[key] = R;
+    }
+  }
+  s.R3 = R;
+  s.nb3 = s.nz * ((s.ny + R - 1) / R);
+  return MM_OK;
+}
+
 int status_of(int done) {
   switch (done) {
     case 1: return MM_OK;
@@ -959,7 +1064,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   const size_t nspec = (size_t)(s.M + 1) * 3 * nz * ny;
   const size_t nB = full ? (size_t)(s.M + 1) * s.Py * 3 * nz : 0;
   s.nblk = local_blocks(s.N);
-  const size_t npart = (size_t)(s.nblk > s.nb3 ? s.nblk : s.nb3) * kNPartial;
+  // per-block sums: room for one row per block (the smallest tile)
+  const size_t npart = (size_t)(s.nblk > nz * ny ? s.nblk : nz * ny) * kNPartial;
   bool ok = hipMalloc(&s.Tt, nT * creal) == hipSuccess &&
             hipMalloc(&s.spec, nspec * 2 * creal) == hipSuccess &&
             hipMalloc(&s.twx, (size_t)s.Px * 2 * creal) == hipSuccess &&
@@ -1010,6 +1116,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   launch_twiddles(c->stream, s.twy, s.Py, sp);
   if (full) launch_twiddles(c->stream, s.twz, s.Pz, sp);
   int rc = full ? build_tensor3d(c, s) : build_tensor(c, s);
+  if (rc == MM_OK) rc = choose_rows(c, s);
   if (rc != MM_OK) {
     free_sample(s);
     return rc;
@@ -1319,12 +1426,26 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->batched = value != 0.0;
   } else if (!std::strcmp(key, "refine")) {
     c->refine = value != 0.0;
+  } else if (!std::strcmp(key, "autotune")) {
+    c->autotune = value != 0.0;
+  } else if (!std::strcmp(key, "rows_per_block")) {
+    if (value < 0 || value > 64 || value != std::floor(value))
+      return fail(c, MM_EINVAL, "rows_per_block is 0 (automatic) or a tile size");
+    c->rows_forced = (int)value;
   } else if (!std::strcmp(key, "demag_path")) {
     if (value != 0 && value != 1 && value != 2) return fail(c, MM_EINVAL, "demag_path is 0, 1 or 2");
     c->path_pref = (int)value;
   } else {
     return fail(c, MM_EINVAL, std::string("unknown option ") + key);
   }
+  return MM_OK;
+}
+
+int mm_rows_per_block(mm_ctx* c, int sample, int* rows) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!rows) return fail(c, MM_EINVAL, "null pointer");
+  *rows = c->smp[sample].R3;
   return MM_OK;
 }
 

@@ -421,3 +421,57 @@ def test_error_paths(torch_cuda):
     with pytest.raises(ValueError):
         ctx.heff(0, torch.zeros(5, dtype=torch.float64, device="cuda"))
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", [(100, 40, 2), (20, 10, 1), (12, 10, 6)])
+def test_row_tiles_agree(torch_cuda, prec, shape):
+    """Every valid rows-per-block tile of the x passes (the autotuner's
+    search space) gives the oracle's field and the same first iterates:
+    tiles change only the grouping of the per-block sums (last-bit changes
+    of the BB step, which BB amplifies over later iterations)."""
+    from paper_1405_2728_amd import Context, MMError
+    torch = torch_cuda
+    nx, ny, nz = shape
+    d = (5e-9,) * 3
+    say("case row tiles", prec, shape)
+    rng = np.random.default_rng(8)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    P = of.Problem(nx, ny, nz, *d, Ms=8e5, A=1.3e-11, Ku=500.0, u=(1, 0, 0), H_ext=(1e4, 0, 0))
+    Ho = P.heff(m0)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    runs = {}
+    for R in range(1, 9):
+        ctx = Context(prec)
+        ctx.set_option("rows_per_block", R)
+        try:
+            ctx.set_geometry(0, nx, ny, nz, *d)
+        except MMError as e:
+            assert e.code == -1
+            ctx.close()
+            continue
+        assert ctx.rows_per_block(0) == R
+        ctx.set_material(0, 8e5, 1.3e-11, 500.0, (1, 0, 0))
+        ctx.set_field(0, (1e4, 0, 0))
+        m = torch.tensor(m0, device="cuda")
+        H = ctx.heff(0, m).cpu().numpy()
+        assert rel(H, Ho) < tol
+        # FP64: the first 10 iterates; mixed: the first two (tau0, then the
+        # first BB step), since a last-bit change of tau changes the FP32
+        # roundings of m - mref, which a random start amplifies
+        ctx.minimize_to_tol(0, m, tol=0.0, max_iter=10 if prec == "fp64" else 2)
+        runs[R] = (H, m.cpu().numpy())
+        ctx.close()
+    say("  valid tiles", sorted(runs))
+    assert 1 in runs and len(runs) >= 2
+    H1, m1 = runs[1]
+    for R, (H, m) in runs.items():
+        assert rel(H, H1) < 1e-13
+        assert np.max(np.abs(m - m1)) < 1e-8
+    # the autotuner picks one of them
+    ctx = Context(prec)
+    ctx.set_option("autotune", 1)
+    ctx.set_geometry(0, nx, ny, nz, *d)
+    say("  autotuned tile", ctx.rows_per_block(0))
+    assert ctx.rows_per_block(0) in runs
+    ctx.close()

@@ -98,6 +98,13 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"demag_path", 0.0) == 0
         assert lib.mm_set_option(h, b"refine", 0.0) == 0
         assert lib.mm_set_option(h, b"refine", 1.0) == 0
+        assert lib.mm_set_option(h, b"autotune", 1.0) == 0
+        assert lib.mm_set_option(h, b"rows_per_block", -1.0) == -1
+        assert lib.mm_set_option(h, b"rows_per_block", 2.5) == -1
+        assert lib.mm_set_option(h, b"rows_per_block", 3.0) == 0
+        assert lib.mm_set_option(h, b"rows_per_block", 0.0) == 0
+        r = C.c_int()
+        assert lib.mm_rows_per_block(h, 0, C.byref(r)) == -5
     finally:
         lib.mm_destroy(h)
     lib.mm_destroy(None)
