@@ -71,30 +71,38 @@ def parse():
     return p.parse_args()
 
 
-def run_gpu(prec, steps, warmup, w, profile, field=0):
+def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False):
     """Warm up, then time `steps` iterations.  With `profile` ("all" or a
     list of kernel names), the library records HIP events around those
     kernels' launches in the timed region (on the library's stream) and the
     per-kernel averages are returned.  The x-pass tile comes from the
-    library's autotuner (timed at set-up, outside the timed region)."""
+    library's autotuner (timed at set-up, outside the timed region).  With
+    `graph`, batches of poll_every iterations replay a captured HIP graph
+    (on a stream of its own)."""
+    import contextlib
     import torch
     from paper_1405_2728_amd import Context
     nx, ny, nz = w["n"]
-    ctx = Context(prec)
+    stream = torch.cuda.Stream() if graph else None
+    ctx = Context(prec, stream=stream)
+    ctx.set_option("use_graph", 1 if graph else 0)
     ctx.set_option("autotune", 1)
     ctx.set_geometry(0, nx, ny, nz, *w["d"])
     rows = ctx.rows_per_block(0)
     ctx.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
     ctx.set_field(0, w["fields"][field])
     m = torch.tensor(w["m0"], dtype=torch.float64, device="cuda")
-    ctx.minimize_to_tol(0, m, tol=0.0, max_iter=warmup)
     torch.cuda.synchronize()
-    if profile:
-        ctx.profile(profile)
-    t0 = time.perf_counter()
-    r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    on = torch.cuda.stream(stream) if graph else contextlib.nullcontext()
+    with on:
+        ctx.minimize_to_tol(0, m, tol=0.0, max_iter=warmup)
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile(profile)
+        t0 = time.perf_counter()
+        r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
     prof = ctx.profile_read() if profile else None
     if profile:
         ctx.profile(None)
@@ -291,7 +299,9 @@ def main():
     label = "x".join(str(v) for v in w["n"])
     if a.quick:
         q = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field)
+        g = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field, graph=True)
         print(json.dumps({"value": q["iters"] / q["seconds"], "unit": "iters/s",
+                          "graph_value": g["iters"] / g["seconds"],
                           "precision": a.prec, "steps": a.steps}))
         return
     # timed region (no events)

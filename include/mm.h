@@ -228,8 +228,11 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
 /* Options (numeric): "tau0" (m/A; 0 = 1e-3/Ms), "poll_every" (iterations
  * between host checks of the stop flag, default 32), "stall_iters" (mixed
  * form without defect correction: iterations without a new torque minimum
- * before MM_STALLED, default 500; 0 disables), "use_graph" (1 = replay iteration batches as a HIP
- * graph), "demag_path" (0 = automatic: thin-film path for nz <= 4, full 3-D
+ * before MM_STALLED, default 500; 0 disables), "use_graph" (1, with a
+ * non-null stream: mm_minimize_to_tol and mm_hysteresis_sweep replay each
+ * batch of poll_every iterations after the first as one captured HIP graph;
+ * mm_minimize_to_tol keeps its graph per sample while m, poll_every, the
+ * correction and the material stay the same; not while kernels are timed), "demag_path" (0 = automatic: thin-film path for nz <= 4, full 3-D
  * path otherwise; 1 = thin-film path only; 2 = full 3-D path also for
  * nz <= 4; read by mm_set_geometry), "refine" (mixed form, default 1:
  * defect correction of the minimiser iterations.  Every poll_every

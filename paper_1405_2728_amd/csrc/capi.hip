@@ -83,6 +83,12 @@ struct Sample {
   double* mref = nullptr;
   double* hdref = nullptr;
   long long ref_age = 0;      // iterations since the last reference pass
+  // captured batch of poll_every minimiser iterations (use_graph), valid for
+  // the m buffer, batch length, correction flag and material it was made with
+  hipGraphExec_t it_graph = nullptr;
+  const double* it_graph_m = nullptr;
+  int it_graph_n = 0, it_graph_ref = 0, it_graph_mat = -1;
+  int mat_version = 0;
   int64_t evals_total = 0, iters_total = 0;
 };
 
@@ -196,6 +202,8 @@ void free_sample(Sample& s) {
   dfree(s.mref);
   dfree(s.hdref);
   s.has_ref = false;
+  if (s.it_graph) (void)hipGraphExecDestroy(s.it_graph);
+  s.it_graph = nullptr;
   if (s.cg_host) (void)hipHostFree(s.cg_host);
   if (s.scal_host) (void)hipHostFree(s.scal_host);
   s.cg_host = nullptr;
@@ -908,16 +916,57 @@ int read_state(mm_ctx* c, Sample& s) {
   return MM_OK;
 }
 
+// Captured batch of poll_every iterations of one sample (made on first use,
+// kept while the m buffer, batch length, correction and material stay).
+// The batch starts with the reference pass when the defect correction is on,
+// as an eager batch does.
+int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
+  const int ref = use_ref(c, s) ? 1 : 0;
+  if (s.it_graph && s.it_graph_m == m && s.it_graph_n == c->poll_every && s.it_graph_ref == ref &&
+      s.it_graph_mat == s.mat_version)
+    return MM_OK;
+  if (s.it_graph) (void)hipGraphExecDestroy(s.it_graph);
+  s.it_graph = nullptr;
+  hipGraph_t g = nullptr;
+  s.ref_age = kRefStale;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, s, m);
+    e = hipStreamEndCapture(c->stream, &g);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&s.it_graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    s.it_graph = nullptr;
+    return fail(c, MM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  s.it_graph_m = m;
+  s.it_graph_n = c->poll_every;
+  s.it_graph_ref = ref;
+  s.it_graph_mat = s.mat_version;
+  return MM_OK;
+}
+
 int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
   launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
                      stall_of(c, s), 0, s.H);
   s.ref_age = kRefStale;
+  // full batches after the first replay a captured graph (use_graph on a
+  // non-null stream, kernels not being timed); the first batch runs eagerly
+  const bool graph = c->use_graph && c->stream != nullptr && c->prof == 0;
   // a run evaluates at most max_iter + 1 times: enqueue no iteration beyond
   // that (such launches would only read the stop flag and return)
   long long left = (long long)max_iter + 1;
-  for (;;) {
+  for (int nbatch = 0;; ++nbatch) {
     const long long batch = left < 1 ? 1 : (left < c->poll_every ? left : c->poll_every);
-    for (long long q = 0; q < batch; ++q) enqueue_iteration(c, s, m);
+    if (graph && nbatch > 0 && batch == c->poll_every) {
+      int rc = ensure_iter_graph(c, s, m);
+      if (rc != MM_OK) return rc;
+      HIPCHK(c, hipGraphLaunch(s.it_graph, c->stream));
+      s.ref_age = c->poll_every;   // as after an eager batch
+    } else {
+      for (long long q = 0; q < batch; ++q) enqueue_iteration(c, s, m);
+    }
     left -= batch;
     HIPCHK(c, hipGetLastError());
     int rc = read_state(c, s);
@@ -1159,6 +1208,7 @@ int mm_set_material(mm_ctx* c, int sample, double Ms, double A, double Ku, const
   }
   s.has_mat = true;
   s.ref_age = kRefStale;   // the reference field scales with Ms
+  ++s.mat_version;         // material constants are baked into captured launches
   launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
   HIPCHK(c, hipGetLastError());
   return MM_OK;

@@ -183,10 +183,12 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
 // spectrum X[0..M]; natural index k is stored at wx_pad(k) = k + k/8 so that
 // the permuted writes of the wave FFT (lanes 8 apart) avoid bank conflicts.
 // Global traffic goes through LDS so that every block moves contiguous
-// chunks of 3 R values per kx.
+// chunks of 3 R values per kx.  The region length is 3 mod 8 elements, so
+// that the 3 R regions read or written at one kx (one per lane of a chunk)
+// start on different LDS banks.
 // ---------------------------------------------------------------------------
 template <int VL>
-__host__ __device__ constexpr int wx_region() { return VL * 72 + 8; }
+__host__ __device__ constexpr int wx_region() { return VL * 72 + 11; }
 __device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
 
 // Body of the forward x pass for logical block L (rows z, y0 .. y0+R-1).

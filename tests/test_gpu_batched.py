@@ -118,3 +118,42 @@ def test_batched_sweep_stationary(torch_cuda):
         say("  sample", k, "oracle torque", T)
         assert T < 1e-6 * 1.001
         assert np.allclose(mavg[k, -1], out[k].reshape(3, -1).mean(axis=1), atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_minimize_graph_replays_equal_eager(torch_cuda, prec):
+    """mm_minimize_to_tol with use_graph replays one captured batch of
+    poll_every iterations (host polls, synchronisations and eager work in
+    between): every run equals the eager run bitwise, also with the cached
+    graph on a second start and after a material change (recapture)."""
+    torch = torch_cuda
+    from paper_1405_2728_amd import Context
+    say("case minimize graph replay", prec)
+    n = (100, 40, 2)
+    rng = np.random.default_rng(77)
+    starts = [synth.uniform_with_noise(synth.tilted(a), *n, 0.2, rng) for a in (20.0, 160.0)]
+    out = {}
+    for graph in (False, True):
+        stream = torch.cuda.Stream()
+        ctx = Context(prec, stream=stream)
+        ctx.set_option("use_graph", 1 if graph else 0)
+        ctx.set_option("poll_every", 16)
+        ctx.set_geometry(0, *n, 5e-9, 5e-9, 5e-9)
+        res = []
+        m = torch.zeros((3,) + n[::-1], dtype=torch.float64, device="cuda")
+        for k, (Ku, m0) in enumerate([(500.0, starts[0]), (500.0, starts[1]), (1500.0, starts[1])]):
+            ctx.set_material(0, 8e5, 1.3e-11, Ku, (1.0, 0.0, 0.0))
+            ctx.set_field(0, (-3e3, 1e3, 0.0))
+            m.copy_(torch.tensor(m0, device="cuda"))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                r = ctx.minimize_to_tol(0, m, tol=1e-7, max_iter=3000)
+                stream.synchronize()
+            res.append((r["iters"], r["status"], m.cpu().numpy()))
+            say("  graph", graph, "run", k, "iters", r["iters"], "status", r["status"])
+        ctx.close()
+        out[graph] = res
+    for a, b in zip(out[False], out[True]):
+        assert a[0] == b[0] and a[1] == b[1]
+        assert np.array_equal(a[2], b[2])
+    assert all(r[0] > 3 * 16 for r in out[True])
