@@ -307,7 +307,8 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
                                              const T* __restrict__ Tt, int tstride, T scale,
                                              const cx<T>* __restrict__ twy,
                                              const int* __restrict__ done, int kx) {
-  if (done != nullptr && *done != 0) return;
+  // the stop flag is read while the first column loads are in flight
+  const int dn = done != nullptr ? *done : 0;
   constexpr int n = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int DC = 2;                       // slots exchanged per round
@@ -334,6 +335,7 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
   cx<T> xin[2][VL];
 #pragma unroll
   for (int r = 0; r < VL; ++r) xin[0][r] = load(0, lane + 64 * r);
+  if (dn != 0) return;             // before any LDS copy is started
   // tensor slab -> LDS, 16 bytes per lane, no registers involved
   auto stage_tensor = [&](const T* slab_src) {
     const int nchunk = tstride * (int)sizeof(T) / 16;

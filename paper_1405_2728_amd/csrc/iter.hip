@@ -203,13 +203,17 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
-  bool upd = false;
+  // The state is read while the first cells' loads are in flight: nothing
+  // branches on it before they are issued, and a finished run (done) writes
+  // nothing and leaves after phase 1 (the flag is the same for the block).
+  int done = 0, pend = 0;
   double tau = 0.0;
   if (st != nullptr) {
-    if (st->done != 0) return;
-    upd = st->pending != 0 && mcopy == nullptr;
+    done = st->done;
+    pend = st->pending;
     tau = st->last_tau;
   }
+  const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
   T* smr = reinterpret_cast<T*>(smem);
@@ -233,7 +237,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             mi[u][c] = m[(size_t)c * N + row0 + idx];
-            gi[u][c] = upd ? g[(size_t)c * N + row0 + idx] : 0.0;
+            gi[u][c] = g != nullptr ? g[(size_t)c * N + row0 + idx] : 0.0;
           }
         }
       }
@@ -253,7 +257,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
             mi[u][c] = mo[c];
           }
         }
-        if (mcopy != nullptr) {
+        if (mcopy != nullptr && done == 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) mcopy[(size_t)c * N + i] = mi[u][c];
         }
@@ -267,6 +271,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
       }
     }
   }
+  if (done != 0) return;
   // zero padding x in [nx, 2M)
   const int jz = nx >> 1;   // first complex slot holding padding (its .y if nx is odd)
   for (int idx = tid; idx < rows * 3 * (M - jz); idx += nthr) {
@@ -340,7 +345,10 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
-  if (a.done != nullptr && *a.done != 0) return;
+  // state read while the spectrum loads are in flight; a finished run leaves
+  // after phase 1 (LDS writes only)
+  const int done = a.done != nullptr ? *a.done : 0;
+  const long long kst = a.st != nullptr ? a.st->k : 0;
   if (a.Hdyn != nullptr)
     for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
   extern __shared__ __align__(16) unsigned char smem[];
@@ -380,6 +388,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
       }
     }
   }
+  if (done != 0) return;
   __syncthreads();
   // phase 2: inverse real transform of one (row, component):
   // Z[k] = (X[k] + conj X[M-k])/2 + i W^-k (X[k] - conj X[M-k])/2, then
@@ -407,7 +416,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   }
   __syncthreads();
   // phase 3: local terms of the rows
-  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
+  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && kst > 0;
   double part[kNPartial] = {};
   {
     constexpr int U = 1;                       // cells per thread per round

@@ -51,7 +51,7 @@ constexpr int kFinishRows = 4;
 __device__ __forceinline__ void finish_block(const double* __restrict__ partials, int nb,
                                              MinState* __restrict__ st, double Ms, double V) {
   __shared__ double scratch[kNPartial * kFinishThreads / 64];
-  if (st->done != 0) return;
+  const int dn = st->done;   // read while the sums' loads are in flight
   double v[kNPartial] = {};
   for (int b0 = threadIdx.x; b0 < nb; b0 += kFinishRows * kFinishThreads) {
     double x[kFinishRows][kNPartial];
@@ -69,6 +69,7 @@ __device__ __forceinline__ void finish_block(const double* __restrict__ partials
         v[q] = q == kPartMax ? fmax(v[q], x[u][q]) : v[q] + x[u][q];
     }
   }
+  if (dn != 0) return;
   bool is_max[kNPartial];
   for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
   block_reduce<kFinishThreads>(v, is_max, scratch);
