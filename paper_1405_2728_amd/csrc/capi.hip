@@ -882,16 +882,21 @@ int choose_rows(mm_ctx* c, Sample& s) {
     if (it != tune_cache().end()) {
       R = it->second;
     } else {
-      double best = 0.0;
-      for (int r : tiles) {
-        double us = 0.0;
-        int rc = time_rows(c, s, r, &us);
-        if (rc != MM_OK) return rc;
-        if (best == 0.0 || us < best) {
-          best = us;
-          R = r;
+      // three rounds over the candidates in turn; each keeps its best window,
+      // so that a transient disturbance of one window decides nothing
+      std::vector<double> best(tiles.size(), 0.0);
+      for (int round = 0; round < 3; ++round) {
+        for (size_t q = 0; q < tiles.size(); ++q) {
+          double us = 0.0;
+          int rc = time_rows(c, s, tiles[q], &us);
+          if (rc != MM_OK) return rc;
+          if (round == 0 || us < best[q]) best[q] = us;
         }
       }
+      size_t qb = 0;
+      for (size_t q = 1; q < tiles.size(); ++q)
+        if (best[q] < best[qb]) qb = q;
+      R = tiles[qb];
       tune_cache()[key] = R;
     }
   }

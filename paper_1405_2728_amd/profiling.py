@@ -46,22 +46,29 @@ def short_name(full):
 
 
 def kernel_stats(db):
+    """Per (kernel, launch shape): calls, average and total duration.  Launches
+    of one kernel with other shapes (the tile autotuner's timing runs, set-up)
+    get rows of their own."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, duration from kernels").fetchall()
+    rows = con.execute("select name, duration, grid_x, workgroup_x from kernels").fetchall()
     agg = defaultdict(list)
-    for name, dur in rows:
-        agg[short_name(name)].append(dur)
+    for name, dur, gx, wx in rows:
+        agg[(short_name(name), int(gx) // max(int(wx), 1), int(wx))].append(dur)
     return {k: {"calls": len(v), "avg_us": sum(v) / len(v) / 1e3, "total_ms": sum(v) / 1e6}
             for k, v in agg.items()}
 
 
-def counter_means(db, counter):
+def counter_means(db, counter, counts=None):
+    """Mean of `counter` per kernel; `counts` (a dict), if given, receives
+    the number of dispatches per kernel."""
     con = sqlite3.connect(db)
     agg = defaultdict(list)
     for name, cn, val in con.execute(
             "select kernel_name, counter_name, value from counters_collection"):
         if cn == counter:
             agg[short_name(name)].append(val)
+    if counts is not None:
+        counts.update({k: len(v) for k, v in agg.items()})
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
 
@@ -70,9 +77,11 @@ def cmd_stats(a):
     lines = ["# %s" % (a.title or os.path.basename(a.db)), ""]
     if a.cmd:
         lines += ["Command: `%s`" % a.cmd, ""]
-    lines += ["| kernel | calls | avg us | total ms |", "|---|---:|---:|---:|"]
+    lines += ["| kernel | blocks | threads/block | calls | avg us | total ms |",
+              "|---|---:|---:|---:|---:|---:|"]
     for k, v in sorted(st.items(), key=lambda kv: -kv[1]["total_ms"]):
-        lines.append("| %s | %d | %.2f | %.3f |" % (k, v["calls"], v["avg_us"], v["total_ms"]))
+        lines.append("| %s | %d | %d | %d | %.2f | %.3f |" % (k[0], k[1], k[2], v["calls"],
+                                                          v["avg_us"], v["total_ms"]))
     print("\n".join(lines))
 
 
@@ -84,7 +93,8 @@ def cmd_traffic(a):
     ckey = max((k for k in cf if k in cw), key=lambda k: min(cf[k], cw[k]))
     f_fetch = a.copy_bytes / (cf[ckey] * 1024.0)
     f_write = a.copy_bytes / (cw[ckey] * 1024.0)
-    fe = counter_means(a.fetch, "FETCH_SIZE")
+    launches = {}
+    fe = counter_means(a.fetch, "FETCH_SIZE", launches)
     wr = counter_means(a.write, "WRITE_SIZE")
     kernels = {}
     for k in set(fe) | set(wr):
@@ -95,10 +105,12 @@ def cmd_traffic(a):
     alias = {"k_xf_w": "xf", "k_xf": "xf", "k_yz_wave": "yz_thin", "k_yz_thin": "yz_thin",
              "k_xil_w": "xil", "k_xil": "xil", "k_update": "update", "k_y3_fwd": "y3_fwd",
              "k_z3": "z3", "k_y3_inv": "y3_inv"}
-    for k in list(kernels):
+    # several instantiations of one pass (the mixed form's double-precision
+    # reference pass, for one): the timing name takes the most launched one
+    for k in sorted(kernels, key=lambda k: -launches.get(k, 0)):
         base = k.split("<")[0]
         if base in alias:
-            kernels.setdefault(alias[base], kernels[k])
+            kernels.setdefault(alias[base], dict(kernels[k], instance=k))
     out = {"precision": a.prec, "source_hash": source_hash(),
            "calibration": {"copy_kernel": ckey, "copy_bytes": a.copy_bytes,
                            "fetch_factor": f_fetch, "write_factor": f_write},
