@@ -854,14 +854,16 @@ int time_rows(mm_ctx* c, Sample& s, int R, double* us) {
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   pass();
   pass();
-  HIPCHK(c, hipEventRecord(e0, st));
-  for (int q = 0; q < kReps; ++q) pass();
-  HIPCHK(c, hipEventRecord(e1, st));
-  HIPCHK(c, hipEventSynchronize(e1));
+  hipError_t e = hipEventRecord(e0, st);
+  for (int q = 0; q < kReps && e == hipSuccess; ++q) pass();
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
-  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   c->ev_pool.push_back(e0);
   c->ev_pool.push_back(e1);
+  if (e != hipSuccess) return fail(c, MM_EHIP, std::string("tile timing: ") + hipGetErrorString(e));
   *us = 1e3 * ms / kReps;
   return MM_OK;
 }
