@@ -115,6 +115,7 @@ struct mm_ctx {
   int refine = 1;               // single-precision form: defect correction on
   int autotune = 0;             // 1: time the x-pass tiles at mm_set_geometry
   int rows_forced = 0;          // > 0: rows per block of the x passes (tests)
+  int radix7 = 1;               // 1: transform length 448 = 7 * 64 where it suffices
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -144,8 +145,18 @@ int next_pow2(int n) {
   return p;
 }
 
-int pad_x(int nx) { return nx < 2 ? 2 : next_pow2(2 * nx - 1); }
-int pad_thin_y(int ny) { return next_pow2(2 * ny - 1); }
+// Padded lengths: powers of two >= 2n - 1, except that with r7 the wave
+// FFT length 448 = 7 * 64 replaces 512 where it suffices (x: Px = 896 for
+// 2nx - 1 in 513..896; thin-film y: Py = 448 for 2ny - 1 in 257..448).
+int pad_x(int nx, bool r7) {
+  if (nx < 2) return 2;
+  const int n = 2 * nx - 1;
+  return r7 && n > 512 && n <= 896 ? 896 : next_pow2(n);
+}
+int pad_thin_y(int ny, bool r7) {
+  const int n = 2 * ny - 1;
+  return r7 && n > 256 && n <= 448 ? 448 : next_pow2(n);
+}
 int pad_3d(int n) {
   const int p = next_pow2(2 * n - 1);
   return p < 64 ? 64 : p;
@@ -153,11 +164,11 @@ int pad_3d(int n) {
 
 // Demag path for a grid: the thin-film path for at most 4 layers (unless the
 // full 3-D path is asked for), the full 3-D path otherwise.
-int choose_path(int prec, int pref, int nx, int ny, int nz) {
+int choose_path(int prec, int pref, int nx, int ny, int nz, bool r7 = true) {
   if (nx < 1 || ny < 1 || nz < 1) return PATH_NONE;
   if (nx > (1 << 14) || ny > (1 << 13)) return PATH_NONE;
-  if (pad_x(nx) / 2 > 8192) return PATH_NONE;
-  const bool thin_ok = yz_thin_fits(nz, pad_thin_y(ny), prec == MM_MIXED);
+  if (pad_x(nx, r7) / 2 > 8192) return PATH_NONE;
+  const bool thin_ok = yz_thin_fits(nz, pad_thin_y(ny, r7), prec == MM_MIXED);
   const bool full_ok = full3d_len_ok(pad_3d(ny)) && full3d_len_ok(pad_3d(nz));
   if (pref == 1) return thin_ok ? PATH_THIN : PATH_NONE;
   if (pref == 2) return full_ok ? PATH_3D : PATH_NONE;
@@ -634,7 +645,8 @@ struct BatchPlan {
 };
 
 bool batchable(const mm_ctx* c, const Sample& s) {
-  return s.path == PATH_THIN && (s.M == 64 || s.M == 128 || s.M == 256 || s.M == 512) &&
+  return s.path == PATH_THIN &&
+         (s.M == 64 || s.M == 128 || s.M == 256 || s.M == 448 || s.M == 512) &&
          yz_wave_ok(s.nz, s.Py) && (!single(c) || !c->refine || s.has_ref);
 }
 
@@ -804,11 +816,13 @@ void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
 // The x passes (xf, xil) work on R rows per block.  With the autotune
 // option, mm_set_geometry times every valid R on the sample's own buffers
 // (both passes, no update, outputs discarded) and keeps the fastest; the
-// choice is cached per (precision, grid, path) for the process.
+// choice is cached per (precision, grid, path, padded lengths) for the
+// process.
 struct TuneKey {
-  int sp, nx, ny, nz, path;
+  int sp, nx, ny, nz, path, Px, Py;
   bool operator<(const TuneKey& o) const {
-    return std::tie(sp, nx, ny, nz, path) < std::tie(o.sp, o.nx, o.ny, o.nz, o.path);
+    return std::tie(sp, nx, ny, nz, path, Px, Py) <
+           std::tie(o.sp, o.nx, o.ny, o.nz, o.path, o.Px, o.Py);
   }
 };
 
@@ -825,7 +839,7 @@ std::mutex& tune_mutex() {
 // Valid tiles: the wave passes take 192 R threads (R <= 4); the LDS passes
 // up to the heuristic's bound (LDS and threads per block); never above ny.
 std::vector<int> row_tiles(int M, int ny, bool sp) {
-  const bool wave = M == 64 || M == 128 || M == 256 || M == 512;
+  const bool wave = M == 64 || M == 128 || M == 256 || M == 448 || M == 512;
   const int hi = wave ? 4 : rows_per_block(M, ny, sp);
   std::vector<int> v;
   for (int r = 1; r <= hi && r <= ny; ++r)
@@ -878,7 +892,7 @@ int choose_rows(mm_ctx* c, Sample& s) {
     if (!ok) return fail(c, MM_EINVAL, "rows_per_block is not a valid tile for this grid");
     R = c->rows_forced;
   } else if (c->autotune && tiles.size() > 1) {
-    const TuneKey key{sp ? 1 : 0, s.nx, s.ny, s.nz, s.path};
+    const TuneKey key{sp ? 1 : 0, s.nx, s.ny, s.nz, s.path, s.Px, s.Py};
     std::lock_guard<std::mutex> lock(tune_mutex());
     auto it = tune_cache().find(key);
     if (it != tune_cache().end()) {
@@ -1089,7 +1103,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
       !std::isfinite(dy) || !std::isfinite(dz))
     return fail(c, MM_EINVAL, "grid sizes must be >= 1 and cell sizes positive");
   if ((long long)nx * ny * nz > (1LL << 30)) return fail(c, MM_EINVAL, "grid too large");
-  const int path = choose_path(c->prec, c->path_pref, nx, ny, nz);
+  const bool r7 = c->radix7 != 0;
+  const int path = choose_path(c->prec, c->path_pref, nx, ny, nz, r7);
   if (path == PATH_NONE)
     return fail(c, MM_EUNSUPPORTED, "grid shape not supported by this build's kernels");
   (void)hipStreamSynchronize(c->stream);
@@ -1106,10 +1121,10 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.dx = dx; s.dy = dy; s.dz = dz;
   s.V = dx * dy * dz;
   s.path = path;
-  s.Px = pad_x(nx);
+  s.Px = pad_x(nx, r7);
   s.M = s.Px / 2;
   const bool full = path == PATH_3D;
-  s.Py = full ? pad_3d(ny) : pad_thin_y(ny);
+  s.Py = full ? pad_3d(ny) : pad_thin_y(ny, r7);
   s.Pz = full ? pad_3d(nz) : 1;
   const bool sp = single(c);
   s.R3 = rows_per_block(s.M, ny, sp);
@@ -1139,7 +1154,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
             hipHostMalloc((void**)&s.host3, 3 * sizeof(double), hipHostMallocDefault) == hipSuccess;
   // double-precision reference of the single-precision form, where the
   // double-precision kernels handle the same path for this grid
-  if (ok && sp && choose_path(MM_FP64, c->path_pref, nx, ny, nz) == path) {
+  if (ok && sp && choose_path(MM_FP64, c->path_pref, nx, ny, nz, r7) == path) {
     s.rR3 = rows_per_block(s.M, ny, false);
     s.rtstride = full ? tensor3_row(s.Pz, false) : thin_tensor_stride(nz, s.Py, false);
     const size_t nTr = (size_t)(s.M + 1) * (full ? (size_t)(s.Py / 2 + 1) : 1) * s.rtstride;
@@ -1483,6 +1498,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->batched = value != 0.0;
   } else if (!std::strcmp(key, "refine")) {
     c->refine = value != 0.0;
+  } else if (!std::strcmp(key, "radix7")) {
+    c->radix7 = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
   } else if (!std::strcmp(key, "rows_per_block")) {

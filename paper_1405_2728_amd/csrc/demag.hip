@@ -562,16 +562,18 @@ void launch_fwd_x(hipStream_t s, const double* in, int in_row_stride, int nx_in,
   const size_t lds = (size_t)vals * sizeof(cx<T>);
   const int nrb = (rows + R - 1) / R;
   dim3 grid(ncomp * nrb);
-  if (vals <= 4LL * 1024) {
+  if (vals <= 512LL * fft_vpt_cap(M, 8)) {
     auto k = k_fwd_x<T, 8>;
     set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 8)), lds, s, in, in_row_stride, nx_in, rows,
-                       ncomp, Px, R, (cx<T>*)out, (const cx<T>*)twx, done);
+    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, fft_vpt_cap(M, 8))), lds, s, in,
+                       in_row_stride, nx_in, rows, ncomp, Px, R, (cx<T>*)out, (const cx<T>*)twx,
+                       done);
   } else {
     auto k = k_fwd_x<T, 16>;
     set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 16)), lds, s, in, in_row_stride, nx_in,
-                       rows, ncomp, Px, R, (cx<T>*)out, (const cx<T>*)twx, done);
+    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, fft_vpt_cap(M, 16))), lds, s, in,
+                       in_row_stride, nx_in, rows, ncomp, Px, R, (cx<T>*)out, (const cx<T>*)twx,
+                       done);
   }
 }
 
@@ -583,29 +585,30 @@ void launch_inv_x(hipStream_t s, const void* in, int rows, int ncomp, int nx_out
   const size_t lds = (size_t)vals * sizeof(cx<T>);
   const int nrb = (rows + R - 1) / R;
   dim3 grid(ncomp * nrb);
-  if (vals <= 4LL * 1024) {
+  if (vals <= 512LL * fft_vpt_cap(M, 8)) {
     auto k = k_inv_x<T, 8>;
     set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 8)), lds, s, (const cx<T>*)in, rows, ncomp,
-                       nx_out, Px, R, out, (const cx<T>*)twx, done);
+    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, fft_vpt_cap(M, 8))), lds, s,
+                       (const cx<T>*)in, rows, ncomp, nx_out, Px, R, out, (const cx<T>*)twx, done);
   } else {
     auto k = k_inv_x<T, 16>;
     set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 16)), lds, s, (const cx<T>*)in, rows, ncomp,
-                       nx_out, Px, R, out, (const cx<T>*)twx, done);
+    hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, fft_vpt_cap(M, 16))), lds, s,
+                       (const cx<T>*)in, rows, ncomp, nx_out, Px, R, out, (const cx<T>*)twx, done);
   }
 }
 
 template <typename T>
 void launch_fft_cols(hipStream_t s, void* data, int n, int nseq, const void* tw) {
-  int per = 4096 / n;
-  if (per < 1) per = 1;   // n <= 4096: at most 512 threads of 8 values
+  const int cap = fft_vpt_cap(n, 8);   // values per thread (7 with a radix-7 stage)
+  int per = 512 * cap / n;
+  if (per < 1) per = 1;   // n <= 512 cap: at most 512 threads
   const long long vals = (long long)per * n;
   const size_t lds = (size_t)vals * sizeof(cx<T>);
   dim3 grid((nseq + per - 1) / per);
   auto k = k_fft_cols<T, 8>;
   set_lds(k, lds);
-  hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, 8)), lds, s, (cx<T>*)data, n, nseq, per,
+  hipLaunchKernelGGL(k, grid, dim3(threads_for(vals, cap)), lds, s, (cx<T>*)data, n, nseq, per,
                      (const cx<T>*)tw);
 }
 
@@ -660,7 +663,9 @@ static void yz_wave_nz(hipStream_t s, void* A, int nz, int ny, int M, const T* T
   }
 }
 
-bool yz_wave_ok(int nz, int Py) { return nz >= 1 && nz <= 4 && Py >= 64 && Py <= 512; }
+bool yz_wave_ok(int nz, int Py) {
+  return nz >= 1 && nz <= 4 && (Py == 64 || Py == 128 || Py == 256 || Py == 448 || Py == 512);
+}
 
 template <typename T>
 void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt,
@@ -670,6 +675,7 @@ void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const
       case 64: yz_wave_nz<T, 1>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       case 128: yz_wave_nz<T, 2>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       case 256: yz_wave_nz<T, 4>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 448: yz_wave_nz<T, 7>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       default: yz_wave_nz<T, 8>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
     }
   }
@@ -711,6 +717,7 @@ void launch_yz_batched(hipStream_t s, const BatchDesc* descs, const WorkItem* it
     case 64: yzb_nz<T, 1>(s, descs, items, n_items, nz, tstride); break;
     case 128: yzb_nz<T, 2>(s, descs, items, n_items, nz, tstride); break;
     case 256: yzb_nz<T, 4>(s, descs, items, n_items, nz, tstride); break;
+    case 448: yzb_nz<T, 7>(s, descs, items, n_items, nz, tstride); break;
     default: yzb_nz<T, 8>(s, descs, items, n_items, nz, tstride); break;
   }
 }

@@ -73,10 +73,44 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
   }
 }
 
+// Length 7: with a_j = v_j + v_{7-j}, b_j = v_j - v_{7-j} (j = 1..3),
+// X[k] = v_0 + sum_j a_j cos(2 pi jk/7) + DIR i sum_j b_j sin(2 pi jk/7) and
+// X[7-k] the same with the sine sum negated (k = 1..3).
+template <int DIR, typename T>
+__device__ __forceinline__ void dft7(cx<T>* v) {
+  // cos and sin of 2 pi m / 7, m = 0..6
+  constexpr double c7[7] = {1.0, 0.6234898018587336, -0.22252093395631434, -0.900968867902419,
+                            -0.900968867902419, -0.22252093395631434, 0.6234898018587336};
+  constexpr double s7[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.43388373911755823,
+                            -0.43388373911755823, -0.9749279121818236, -0.7818314824680298};
+  cx<T> a[4], b[4];
+#pragma unroll
+  for (int j = 1; j <= 3; ++j) {
+    a[j] = add(v[j], v[7 - j]);
+    b[j] = sub(v[j], v[7 - j]);
+  }
+  const cx<T> x0 = v[0];
+  v[0] = add(add(x0, a[1]), add(a[2], a[3]));
+#pragma unroll
+  for (int k = 1; k <= 3; ++k) {
+    cx<T> t = x0, u = mk(T(0), T(0));
+#pragma unroll
+    for (int j = 1; j <= 3; ++j) {
+      const int m = (j * k) % 7;
+      t = add(t, scl(a[j], T(c7[m])));
+      u = add(u, scl(b[j], T(s7[m])));
+    }
+    const cx<T> ru = rot90<DIR>(u);
+    v[k] = add(t, ru);
+    v[7 - k] = sub(t, ru);
+  }
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dftR(cx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
   else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 7) dft7<DIR>(v);
   else dft8<DIR>(v);
 }
 
@@ -87,15 +121,20 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int m) {
   return DIR < 0 ? w : conj(w);
 }
 
-// Radix plan of a power-of-two length n: 8s, with one 4 (p % 3 == 2) or two
-// 4s (p % 3 == 1); n = 2 uses a single radix-2 stage.  Encoded as the
-// number of leading radix-4 stages and radix-8 stages.
+// Radix plan of a length n = 2^p or 7 * 2^p: an optional leading radix-7
+// stage, then for the power of two 8s, with one 4 (p % 3 == 2) or two 4s
+// (p % 3 == 1); 2 uses a single radix-2 stage.  Encoded as the number of
+// radix-7, radix-2, radix-4 and radix-8 stages.
 struct FftPlan {
-  int n, n4, n8, n2;
+  int n, n4, n8, n2, n7;
 };
 
 __host__ __device__ inline FftPlan make_plan(int n) {
-  FftPlan p{n, 0, 0, 0};
+  FftPlan p{n, 0, 0, 0, 0};
+  if (n % 7 == 0) {
+    p.n7 = 1;
+    n /= 7;
+  }
   int lg = 0;
   while ((1 << lg) < n) ++lg;
   if (lg == 0) return p;
@@ -108,11 +147,18 @@ __host__ __device__ inline FftPlan make_plan(int n) {
   return p;
 }
 
+// Values per thread that the stages of a length-n plan hold at VPT: a
+// radix-7 stage keeps 7 (VPT/7) values per thread.  Launchers size their
+// blocks with it.
+__host__ __device__ inline int fft_vpt_cap(int n, int vpt) {
+  return n % 7 == 0 ? 7 * (vpt / 7) : vpt;
+}
+
 // One in-place Stockham stage of radix R over nseq sequences of length n
 // stored at buf + s*stride.  Every thread first loads, twiddles and
 // transforms up to VPT/R butterflies into registers, then (after a barrier)
 // stores them: the in-place form needs all loads of a stage to precede its
-// stores, so the caller guarantees nseq*n <= VPT*nthr.
+// stores, so the caller guarantees nseq*n <= fft_vpt_cap(n, VPT)*nthr.
 //   butterfly j of a sequence (0 <= j < n/R), k = j mod Ns:
 //     v[r] = x[j + r n/R] * w^(r k),  w = exp(DIR 2 pi i / (Ns R))
 //     v    = DFT_R(v)
@@ -134,7 +180,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* buf, int n, int Ns, int ns
     if (t < nb) {
       const int s = t / nbs;
       const int j = t - s * nbs;
-      const int k = j & (Ns - 1);
+      const int k = (Ns & (Ns - 1)) == 0 ? j & (Ns - 1) : j % Ns;
       cx<T>* p = buf + s * stride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = p[j + r * nbs];
@@ -157,13 +203,17 @@ __device__ __forceinline__ void stockham_stage(cx<T>* buf, int n, int Ns, int ns
   __syncthreads();
 }
 
-// Full in-place FFT of nseq sequences of power-of-two length n in LDS.
+// Full in-place FFT of nseq sequences of length n = 2^p or 7 * 2^p in LDS.
 // tw: table of exp(-2 pi i m / twn) with twn a multiple of n.
 template <int DIR, int VPT, typename T>
 __device__ void fft_lds(cx<T>* buf, int n, int nseq, int stride, const cx<T>* __restrict__ tw,
                         int twn, int tid, int nthr) {
   const FftPlan p = make_plan(n);
   int Ns = 1;
+  if (p.n7) {
+    stockham_stage<7, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    Ns *= 7;
+  }
   if (p.n2) {
     stockham_stage<2, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
     Ns *= 2;

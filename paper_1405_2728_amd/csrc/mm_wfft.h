@@ -1,5 +1,5 @@
 // Register-resident FFT of one sequence per wavefront (64 lanes), length
-// n = 64 VL with VL in {1, 2, 4, 8}.
+// n = 64 VL with VL in {1, 2, 4, 7, 8}.
 //
 // Forward, natural input: lane l holds x[l + 64 r] in v[r] (r < VL).
 //   S1  DFT_VL over r, twiddle by W_n^(l k1)            (k1 < VL)
@@ -15,7 +15,8 @@
 // Transposes use a wave-private LDS buffer of wfft_buf<VL, HALF>()
 // elements; the index maps are padded (one slot per 8) so that lanes 8
 // apart fall on different banks.  With HALF the buffer holds the groups
-// k1 < VL/2 and k1 >= VL/2 in turn (half the LDS, twice the exchanges).
+// k1 < VL/2 and k1 >= VL/2 in turn (half the LDS, twice the exchanges; even
+// VL only, odd VL always uses the whole buffer).
 // LDS instructions of one wavefront execute in order, so the exchange within
 // a wave needs no block barrier.
 #pragma once
@@ -27,15 +28,22 @@ namespace mmk {
 __device__ __forceinline__ int wf_f1(int k1, int q) { return k1 * 72 + q + (q >> 3); }
 __device__ __forceinline__ int wf_f2(int k1, int c, int a) { return k1 * 72 + c * 9 + a; }
 
+// passes over the k1 groups of a transpose
+template <int VL, bool HALF>
+__host__ __device__ constexpr int wfft_passes() {
+  return (HALF && VL >= 2 && VL % 2 == 0) ? 2 : 1;
+}
+
 template <int VL, bool HALF>
 __host__ __device__ constexpr int wfft_buf() {
-  return (HALF && VL >= 2 ? VL / 2 : VL) * 72;
+  return VL / wfft_passes<VL, HALF>() * 72;
 }
 
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_small(cx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
   else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 7) dft7<DIR>(v);
   else if constexpr (R == 8) dft8<DIR>(v);
 }
 
@@ -45,7 +53,7 @@ template <typename T, int VL, bool HALF, int TS = 1>
 __device__ __forceinline__ void wfft_forward(cx<T> (&v)[VL], cx<T> (&u)[8], cx<T>* lds,
                                              const cx<T>* __restrict__ tw, int lane) {
   constexpr int NG = 8 * VL;
-  constexpr int NP = (HALF && VL >= 2) ? 2 : 1;     // passes over the k1 groups
+  constexpr int NP = wfft_passes<VL, HALF>();       // passes over the k1 groups
   constexpr int KP = VL / NP;                       // k1 groups per pass
   dft_small<VL, -1>(v);
 #pragma unroll
@@ -89,7 +97,7 @@ template <typename T, int VL, bool HALF, int TS = 1>
 __device__ __forceinline__ void wfft_inverse(cx<T> (&u)[8], cx<T> (&v)[VL], cx<T>* lds,
                                              const cx<T>* __restrict__ tw, int lane) {
   constexpr int NG = 8 * VL;
-  constexpr int NP = (HALF && VL >= 2) ? 2 : 1;
+  constexpr int NP = wfft_passes<VL, HALF>();
   constexpr int KP = VL / NP;
   const int k1 = lane >> 3, a = lane & 7, c = lane & 7;
   if (lane < NG) dft8<1>(u);

@@ -74,6 +74,10 @@ SHAPES = [
     ((150, 37, 1), (4e-9, 5e-9, 6e-9)),
     ((90, 7, 3), (5e-9, 5e-9, 5e-9)),
     ((300, 5, 1), (5e-9, 5e-9, 5e-9)),
+    # transform length 448 = 7 * 64 (x padded to 896, thin-film y to 448) at
+    # both ends of its range (2n - 1 just above 512 / 256, and exactly 896 / 448)
+    ((260, 129, 1), (5e-9, 5e-9, 5e-9)),
+    ((448, 224, 2), (4e-9, 5e-9, 3e-9)),
 ]
 
 
@@ -123,7 +127,7 @@ def test_heff_ku_map_and_determinism(torch_cuda):
     ctx.close()
 
 
-@pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (100, 50, 2)])
+@pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (100, 50, 2), (260, 129, 2)])
 def test_heff_mixed_precision(torch_cuda, shape):
     torch = torch_cuda
     nx, ny, nz = shape
@@ -424,7 +428,7 @@ def test_error_paths(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("shape", [(100, 40, 2), (20, 10, 1), (12, 10, 6)])
+@pytest.mark.parametrize("shape", [(100, 40, 2), (20, 10, 1), (12, 10, 6), (300, 150, 1)])
 def test_row_tiles_agree(torch_cuda, prec, shape):
     """Every valid rows-per-block tile of the x passes (the autotuner's
     search space) gives the oracle's field and the same first iterates:
@@ -503,3 +507,34 @@ def test_mixed_without_fp64_reference(torch_cuda):
     assert r["status"] in (0, 2)
     assert T < 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_radix7_padding_matches_powers_of_two(torch_cuda, prec):
+    """The 448-point transforms (x padded to 896, y to 448) and the
+    power-of-two padding (1024, 512) compute the same convolution: fields
+    agree to rounding, and so do the first iterates."""
+    torch = torch_cuda
+    from paper_1405_2728_amd import Context
+    nx, ny, nz = 300, 150, 2
+    d = (5e-9,) * 3
+    say("case radix-7 padding", prec, (nx, ny, nz))
+    rng = np.random.default_rng(23)
+    m0 = synth.uniform_with_noise(synth.tilted(20.0), nx, ny, nz, 0.3, rng)
+    out = {}
+    for r7 in (1, 0):
+        ctx = Context(prec)
+        ctx.set_option("radix7", r7)
+        ctx.set_geometry(0, nx, ny, nz, *d)
+        ctx.set_material(0, 8e5, 1.3e-11, 500.0, (1, 0, 0))
+        ctx.set_field(0, (-1e4, 2e3, 0))
+        m = torch.tensor(m0, device="cuda")
+        H = ctx.heff(0, m).cpu().numpy()
+        ctx.minimize_to_tol(0, m, tol=0.0, max_iter=5)
+        out[r7] = (H, m.cpu().numpy())
+        ctx.close()
+    e = rel(out[1][0], out[0][0])
+    dm = float(np.max(np.abs(out[1][1] - out[0][1])))
+    say("  field rel diff", e, "5-iterate max diff", dm)
+    assert e < (1e-13 if prec == "fp64" else 1e-5)
+    assert dm < (1e-10 if prec == "fp64" else 1e-4)
