@@ -815,7 +815,8 @@ void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
 // ---- tile autotuner: rows per block of the fused x passes -----------------
 // The x passes (xf, xil) work on R rows per block.  With the autotune
 // option, mm_set_geometry times every valid R on the sample's own buffers
-// (both passes, no update, outputs discarded) and keeps the fastest; the
+// (both passes in their minimiser form on scratch data) and keeps the
+// fastest; the
 // choice is cached per (precision, grid, path, padded lengths) for the
 // process.
 struct TuneKey {
@@ -847,21 +848,33 @@ std::vector<int> row_tiles(int M, int ny, bool sp) {
   return v;
 }
 
-// Mean time of one xf + xil pair with R rows per block (microseconds).
+// Mean time of one xf + xil pair with R rows per block (microseconds), in
+// the form they take in a minimiser iteration: pending update, g and s read
+// and written, BB and energy sums.  Scratch data: m is the field-output
+// buffer (set up by prepare_tuning), g and s the sample's own, the state
+// st_eval; the caller clears g and s afterwards.
 int time_rows(mm_ctx* c, Sample& s, int R, double* us) {
   hipStream_t st = c->stream;
   const bool sp = single(c);
-  LocalArgs a = local_args(s);
-  a.m = s.g;   // zeros; no update is applied (no state), nothing is written
+  Sample q = s;                 // material constants, finite even before mm_set_material
+  if (!(q.Ms > 0)) {
+    q.Ms = 8e5;
+    q.A = 1.3e-11;
+  }
+  LocalArgs a = local_args(q);
+  a.m = s.Hd;
+  a.g = s.g;
+  a.s = s.s;
+  a.st = s.st_eval;
   auto pass = [&]() {
     if (sp) {
-      launch_xf<float>(st, s.g, nullptr, nullptr, nullptr, s.nx, s.ny, s.nz, s.Px, R, s.spec, s.twx,
+      launch_xf<float>(st, s.Hd, s.g, s.s, s.st_eval, s.nx, s.ny, s.nz, s.Px, R, s.spec, s.twx,
                        nullptr, nullptr);
-      launch_xil<float>(st, s.spec, a, s.Px, R, nullptr, nullptr, s.twx);
+      launch_xil<float>(st, s.spec, a, s.Px, R, nullptr, s.partials, s.twx);
     } else {
-      launch_xf<double>(st, s.g, nullptr, nullptr, nullptr, s.nx, s.ny, s.nz, s.Px, R, s.spec,
+      launch_xf<double>(st, s.Hd, s.g, s.s, s.st_eval, s.nx, s.ny, s.nz, s.Px, R, s.spec,
                         s.twx, nullptr, nullptr);
-      launch_xil<double>(st, s.spec, a, s.Px, R, nullptr, nullptr, s.twx);
+      launch_xil<double>(st, s.spec, a, s.Px, R, nullptr, s.partials, s.twx);
     }
   };
   constexpr int kReps = 5;
@@ -898,6 +911,18 @@ int choose_rows(mm_ctx* c, Sample& s) {
     if (it != tune_cache().end()) {
       R = it->second;
     } else {
+      // scratch: m = 0x3f3f... in every byte (about 4.8e-4 per component,
+      // finite; the update normalises it), a state with an update pending
+      // and k = 1 (BB sums on)
+      HIPCHK(c, hipMemsetAsync(s.Hd, 0x3f, 3ull * s.N * sizeof(double), c->stream));
+      MinState& h = *s.st_host;
+      std::memset(&h, 0, sizeof(MinState));
+      h.tau = h.last_tau = h.tau0 = 1e-3 / 8e5;
+      h.k = 1;
+      h.pending = 1;
+      h.max_iter = 1;
+      HIPCHK(c, hipMemcpyAsync(s.st_eval, s.st_host, sizeof(MinState), hipMemcpyHostToDevice,
+                               c->stream));
       // three rounds over the candidates in turn; each keeps its best window,
       // so that a transient disturbance of one window decides nothing
       std::vector<double> best(tiles.size(), 0.0);
@@ -1192,6 +1217,9 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
     free_sample(s);
     return rc;
   }
+  // the tile timing ran minimiser passes on g and s: start from zero again
+  HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * sizeof(double), c->stream));
   s.has_geom = true;
   s.has_mat = s.Ms > 0;
   s.evals_total = s.iters_total = 0;
