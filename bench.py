@@ -47,7 +47,7 @@ sys.path.insert(0, ROOT)
 # name -> (synthetic workload id, field index, description, padded grid)
 WORKLOADS = {
     "film": (1, 0, "film 400x200x4 cells of 5 nm (Standard Problem 1 stand-in), "
-                   "BB midpoint minimiser, +50 mT at 1 deg", [1024, 512, 4]),
+                   "BB midpoint minimiser, +50 mT at 1 deg", [896, 448, 4]),
     "cube": (2, 3, "cube 128^3 cells of 2 nm, full 3-D demag, BB midpoint minimiser, "
                    "random start, 60 mT at 2 deg from z", [256, 256, 256]),
 }
