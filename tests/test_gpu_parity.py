@@ -282,6 +282,7 @@ SHAPES_3D = [
     ((1, 40, 6), (5e-9, 5e-9, 5e-9)),
     ((70, 33, 5), (5e-9, 5e-9, 5e-9)),
     ((9, 130, 10), (5e-9, 5e-9, 5e-9)),
+    ((300, 12, 6), (5e-9, 5e-9, 5e-9)),     # x padded to 896 on the 3-D path
 ]
 
 
