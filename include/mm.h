@@ -251,11 +251,13 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * uses a fixed heuristic, so that results do not depend on timing),
  * "rows_per_block" (0 = automatic; otherwise that tile for every later
  * mm_set_geometry, which fails with MM_EINVAL where it is not valid: for
- * testing every tile), "radix7" (default 1, read by mm_set_geometry: a
- * padded x length of 896 and thin-film y length of 448 = 7 * 64 replace
- * 1024 and 512 where they suffice, i.e. for 2 nx - 1 in 513..896 and
- * 2 ny - 1 in 257..448; 0 keeps powers of two).  Unknown keys or values
- * give MM_EINVAL. */
+ * testing every tile), "mixed_radix" (default 1, read by mm_set_geometry:
+ * the padded x length is the smaller of the power of two >= 2 nx - 1 and
+ * the multiple of 128 >= 2 nx - 1 (up to 1024), the thin-film y length the
+ * smaller of the power of two >= 2 ny - 1 and the multiple of 64 (up to
+ * 512), so that transforms of 64 VL points with VL = 3, 5, 6, 7 take the
+ * place of the next power of two; 0 keeps powers of two).  Unknown keys or
+ * values give MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 
 /* Rows per block of the sample's fused x passes (host int output), as the
@@ -268,10 +270,10 @@ int mm_rows_per_block(mm_ctx* ctx, int sample, int* rows);
 int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
 
 /* Whether this build's kernels handle a grid (1) or not (0) with the
- * automatic demag path (and the default "radix7" padding): nx <= 8192;
- * nz <= 4 with 2ny-1 padded (to a power of two, or 448) so that 3 nz Py
- * complex values fit one block, or nz > 4 with ny, nz <= 256 (y and z
- * padded to powers of two in 64..512). */
+ * automatic demag path (and the default "mixed_radix" padding): nx <= 8192;
+ * nz <= 4 with 2ny-1 padded (to a power of two or a multiple of 64) so that
+ * 3 nz Py complex values fit one block, or nz > 4 with ny, nz <= 256 (y and
+ * z padded to powers of two in 64..512). */
 int mm_supported(int prec, int nx, int ny, int nz);
 
 /* Per-kernel timing with HIP events on the context's stream.

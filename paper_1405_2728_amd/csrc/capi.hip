@@ -115,7 +115,7 @@ struct mm_ctx {
   int refine = 1;               // single-precision form: defect correction on
   int autotune = 0;             // 1: time the x-pass tiles at mm_set_geometry
   int rows_forced = 0;          // > 0: rows per block of the x passes (tests)
-  int radix7 = 1;               // 1: transform length 448 = 7 * 64 where it suffices
+  int mixed_radix = 1;          // 1: wave lengths 64 VL (VL = 3, 5, 6, 7) where shorter
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -145,18 +145,18 @@ int next_pow2(int n) {
   return p;
 }
 
-// Padded lengths: powers of two >= 2n - 1, except that with r7 the wave
-// FFT length 448 = 7 * 64 replaces 512 where it suffices (x: Px = 896 for
-// 2nx - 1 in 513..896; thin-film y: Py = 448 for 2ny - 1 in 257..448).
-int pad_x(int nx, bool r7) {
-  if (nx < 2) return 2;
-  const int n = 2 * nx - 1;
-  return r7 && n > 512 && n <= 896 ? 896 : next_pow2(n);
+// Padded lengths >= 2n - 1: powers of two, except that with mixed radix
+// the wave FFT lengths 64 VL (VL = 3, 5, 6, 7) replace the power of two
+// where they are shorter: x Px = 128 VL (half-length transform 64 VL) for
+// 2nx - 1 up to 1024, thin-film y Py = 64 VL for 2ny - 1 up to 512.
+int pad_wave(int n, int unit, bool mr) {
+  const int p = next_pow2(n);
+  if (!mr || n > 8 * unit) return p;
+  const int w = (n + unit - 1) / unit * unit;
+  return w < p ? w : p;
 }
-int pad_thin_y(int ny, bool r7) {
-  const int n = 2 * ny - 1;
-  return r7 && n > 256 && n <= 448 ? 448 : next_pow2(n);
-}
+int pad_x(int nx, bool mr) { return nx < 2 ? 2 : pad_wave(2 * nx - 1, 128, mr); }
+int pad_thin_y(int ny, bool mr) { return pad_wave(2 * ny - 1, 64, mr); }
 int pad_3d(int n) {
   const int p = next_pow2(2 * n - 1);
   return p < 64 ? 64 : p;
@@ -164,11 +164,11 @@ int pad_3d(int n) {
 
 // Demag path for a grid: the thin-film path for at most 4 layers (unless the
 // full 3-D path is asked for), the full 3-D path otherwise.
-int choose_path(int prec, int pref, int nx, int ny, int nz, bool r7 = true) {
+int choose_path(int prec, int pref, int nx, int ny, int nz, bool mr = true) {
   if (nx < 1 || ny < 1 || nz < 1) return PATH_NONE;
   if (nx > (1 << 14) || ny > (1 << 13)) return PATH_NONE;
-  if (pad_x(nx, r7) / 2 > 8192) return PATH_NONE;
-  const bool thin_ok = yz_thin_fits(nz, pad_thin_y(ny, r7), prec == MM_MIXED);
+  if (pad_x(nx, mr) / 2 > 8192) return PATH_NONE;
+  const bool thin_ok = yz_thin_fits(nz, pad_thin_y(ny, mr), prec == MM_MIXED);
   const bool full_ok = full3d_len_ok(pad_3d(ny)) && full3d_len_ok(pad_3d(nz));
   if (pref == 1) return thin_ok ? PATH_THIN : PATH_NONE;
   if (pref == 2) return full_ok ? PATH_3D : PATH_NONE;
@@ -645,8 +645,7 @@ struct BatchPlan {
 };
 
 bool batchable(const mm_ctx* c, const Sample& s) {
-  return s.path == PATH_THIN &&
-         (s.M == 64 || s.M == 128 || s.M == 256 || s.M == 448 || s.M == 512) &&
+  return s.path == PATH_THIN && s.M % 64 == 0 && s.M >= 64 && s.M <= 512 &&
          yz_wave_ok(s.nz, s.Py) && (!single(c) || !c->refine || s.has_ref);
 }
 
@@ -840,7 +839,7 @@ std::mutex& tune_mutex() {
 // Valid tiles: the wave passes take 192 R threads (R <= 4); the LDS passes
 // up to the heuristic's bound (LDS and threads per block); never above ny.
 std::vector<int> row_tiles(int M, int ny, bool sp) {
-  const bool wave = M == 64 || M == 128 || M == 256 || M == 448 || M == 512;
+  const bool wave = M % 64 == 0 && M >= 64 && M <= 512;
   const int hi = wave ? 4 : rows_per_block(M, ny, sp);
   std::vector<int> v;
   for (int r = 1; r <= hi && r <= ny; ++r)
@@ -1128,8 +1127,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
       !std::isfinite(dy) || !std::isfinite(dz))
     return fail(c, MM_EINVAL, "grid sizes must be >= 1 and cell sizes positive");
   if ((long long)nx * ny * nz > (1LL << 30)) return fail(c, MM_EINVAL, "grid too large");
-  const bool r7 = c->radix7 != 0;
-  const int path = choose_path(c->prec, c->path_pref, nx, ny, nz, r7);
+  const bool mr = c->mixed_radix != 0;
+  const int path = choose_path(c->prec, c->path_pref, nx, ny, nz, mr);
   if (path == PATH_NONE)
     return fail(c, MM_EUNSUPPORTED, "grid shape not supported by this build's kernels");
   (void)hipStreamSynchronize(c->stream);
@@ -1146,10 +1145,10 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.dx = dx; s.dy = dy; s.dz = dz;
   s.V = dx * dy * dz;
   s.path = path;
-  s.Px = pad_x(nx, r7);
+  s.Px = pad_x(nx, mr);
   s.M = s.Px / 2;
   const bool full = path == PATH_3D;
-  s.Py = full ? pad_3d(ny) : pad_thin_y(ny, r7);
+  s.Py = full ? pad_3d(ny) : pad_thin_y(ny, mr);
   s.Pz = full ? pad_3d(nz) : 1;
   const bool sp = single(c);
   s.R3 = rows_per_block(s.M, ny, sp);
@@ -1179,7 +1178,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
             hipHostMalloc((void**)&s.host3, 3 * sizeof(double), hipHostMallocDefault) == hipSuccess;
   // double-precision reference of the single-precision form, where the
   // double-precision kernels handle the same path for this grid
-  if (ok && sp && choose_path(MM_FP64, c->path_pref, nx, ny, nz, r7) == path) {
+  if (ok && sp && choose_path(MM_FP64, c->path_pref, nx, ny, nz, mr) == path) {
     s.rR3 = rows_per_block(s.M, ny, false);
     s.rtstride = full ? tensor3_row(s.Pz, false) : thin_tensor_stride(nz, s.Py, false);
     const size_t nTr = (size_t)(s.M + 1) * (full ? (size_t)(s.Py / 2 + 1) : 1) * s.rtstride;
@@ -1526,8 +1525,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->batched = value != 0.0;
   } else if (!std::strcmp(key, "refine")) {
     c->refine = value != 0.0;
-  } else if (!std::strcmp(key, "radix7")) {
-    c->radix7 = value != 0.0;
+  } else if (!std::strcmp(key, "mixed_radix")) {
+    c->mixed_radix = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
   } else if (!std::strcmp(key, "rows_per_block")) {

@@ -53,7 +53,7 @@ k_fwd_x(const double* __restrict__ in, int in_row_stride, int nx_in, int rows, i
     buf[r * M + j] = mk(a, b);
   }
   __syncthreads();
-  fft_lds<-1, VPT>(buf, M, R, M, twx, Px, tid, nthr);
+  fft_lds<-1, VPT, true>(buf, M, R, M, twx, Px, tid, nthr);
   const size_t slab = (size_t)ncomp * rows;
   for (int idx = tid; idx < (M + 1) * R; idx += nthr) {
     const int k = idx / R, r = idx - k * R;
@@ -98,7 +98,7 @@ k_inv_x(const cx<T>* __restrict__ in, int rows, int ncomp, int nx_out, int Px, i
     buf[r * M + k] = Z;
   }
   __syncthreads();
-  fft_lds<1, VPT>(buf, M, R, M, twx, Px, tid, nthr);
+  fft_lds<1, VPT, true>(buf, M, R, M, twx, Px, tid, nthr);
   for (int idx = tid; idx < R * M; idx += nthr) {
     const int r = idx / M, j = idx - r * M;
     const int row = r0 + r;
@@ -125,7 +125,7 @@ k_fft_cols(cx<T>* __restrict__ data, int n, int nseq, int per_block, const cx<T>
   cx<T>* base = data + (size_t)s0 * n;
   for (int idx = tid; idx < ns * n; idx += nthr) buf[idx] = base[idx];
   __syncthreads();
-  fft_lds<-1, VPT>(buf, n, ns, n, tw, n, tid, nthr);
+  fft_lds<-1, VPT, true>(buf, n, ns, n, tw, n, tid, nthr);
   for (int idx = tid; idx < ns * n; idx += nthr) base[idx] = buf[idx];
 }
 
@@ -664,7 +664,7 @@ static void yz_wave_nz(hipStream_t s, void* A, int nz, int ny, int M, const T* T
 }
 
 bool yz_wave_ok(int nz, int Py) {
-  return nz >= 1 && nz <= 4 && (Py == 64 || Py == 128 || Py == 256 || Py == 448 || Py == 512);
+  return nz >= 1 && nz <= 4 && Py % 64 == 0 && Py >= 64 && Py <= 512;
 }
 
 template <typename T>
@@ -674,7 +674,10 @@ void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const
     switch (Py) {
       case 64: yz_wave_nz<T, 1>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       case 128: yz_wave_nz<T, 2>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 192: yz_wave_nz<T, 3>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       case 256: yz_wave_nz<T, 4>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 320: yz_wave_nz<T, 5>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 384: yz_wave_nz<T, 6>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       case 448: yz_wave_nz<T, 7>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
       default: yz_wave_nz<T, 8>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
     }
@@ -716,7 +719,10 @@ void launch_yz_batched(hipStream_t s, const BatchDesc* descs, const WorkItem* it
   switch (Py) {
     case 64: yzb_nz<T, 1>(s, descs, items, n_items, nz, tstride); break;
     case 128: yzb_nz<T, 2>(s, descs, items, n_items, nz, tstride); break;
+    case 192: yzb_nz<T, 3>(s, descs, items, n_items, nz, tstride); break;
     case 256: yzb_nz<T, 4>(s, descs, items, n_items, nz, tstride); break;
+    case 320: yzb_nz<T, 5>(s, descs, items, n_items, nz, tstride); break;
+    case 384: yzb_nz<T, 6>(s, descs, items, n_items, nz, tstride); break;
     case 448: yzb_nz<T, 7>(s, descs, items, n_items, nz, tstride); break;
     default: yzb_nz<T, 8>(s, descs, items, n_items, nz, tstride); break;
   }

@@ -176,7 +176,7 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Wave-FFT variants (M = Px/2 = 64 VL, VL in {1, 2, 4, 7, 8}).  A block holds R
+// Wave-FFT variants (M = Px/2 = 64 VL, VL in 1..8).  A block holds R
 // rows; wave w = 3 r + c transforms component c of row r.  Each (row,
 // component) owns an LDS region of wx_region<VL>() elements, used in turn
 // for the natural-order sequence, the transposes of the wave FFT and the
@@ -539,14 +539,14 @@ static void set_lds(K kernel, size_t bytes) {
                               (int)bytes);
 }
 
-static bool wave_x(int M) { return M == 64 || M == 128 || M == 256 || M == 448 || M == 512; }
+static bool wave_x(int M) { return M % 64 == 0 && M >= 64 && M <= 512; }
 
 int rows_per_block(int M, int ny, bool single) {
   if (wave_x(M)) {
     // short rows: 4 per block (12 waves), fewer and larger blocks; the
-    // longest (M = 448, 512): one row per block (3 waves), more blocks per CU
+    // longest (M >= 384): one row per block (3 waves), more blocks per CU
     if (M <= 256 && ny >= 4) return 4;
-    if (M >= 448) return 1;
+    if (M >= 384) return 1;
     return ny >= 2 ? 2 : 1;
   }
   // 3 R M complex values per block: at most 4096 (VPT 8, 512 threads) and
@@ -591,7 +591,10 @@ void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const Mi
   switch (M) {
     case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
     case 128: xf_wave<T, 2>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 192: xf_wave<T, 3>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
     case 256: xf_wave<T, 4>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 320: xf_wave<T, 5>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 384: xf_wave<T, 6>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
     case 448: xf_wave<T, 7>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
     case 512: xf_wave<T, 8>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
     default: break;
@@ -619,7 +622,10 @@ void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R
   switch (M) {
     case 64: xil_wave<T, 1>(s, in, a, R, Hd_out, partials, twx); return;
     case 128: xil_wave<T, 2>(s, in, a, R, Hd_out, partials, twx); return;
+    case 192: xil_wave<T, 3>(s, in, a, R, Hd_out, partials, twx); return;
     case 256: xil_wave<T, 4>(s, in, a, R, Hd_out, partials, twx); return;
+    case 320: xil_wave<T, 5>(s, in, a, R, Hd_out, partials, twx); return;
+    case 384: xil_wave<T, 6>(s, in, a, R, Hd_out, partials, twx); return;
     case 448: xil_wave<T, 7>(s, in, a, R, Hd_out, partials, twx); return;
     case 512: xil_wave<T, 8>(s, in, a, R, Hd_out, partials, twx); return;
     default: break;
@@ -661,7 +667,10 @@ void launch_x_batched(hipStream_t s, bool inverse, const BatchDesc* descs, const
   switch (M) {
     case 64: xb_launch<T, 1>(s, inverse, descs, items, n_items, R); break;
     case 128: xb_launch<T, 2>(s, inverse, descs, items, n_items, R); break;
+    case 192: xb_launch<T, 3>(s, inverse, descs, items, n_items, R); break;
     case 256: xb_launch<T, 4>(s, inverse, descs, items, n_items, R); break;
+    case 320: xb_launch<T, 5>(s, inverse, descs, items, n_items, R); break;
+    case 384: xb_launch<T, 6>(s, inverse, descs, items, n_items, R); break;
     case 448: xb_launch<T, 7>(s, inverse, descs, items, n_items, R); break;
     default: xb_launch<T, 8>(s, inverse, descs, items, n_items, R); break;
   }

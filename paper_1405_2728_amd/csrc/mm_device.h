@@ -73,44 +73,80 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
   }
 }
 
-// Length 7: with a_j = v_j + v_{7-j}, b_j = v_j - v_{7-j} (j = 1..3),
-// X[k] = v_0 + sum_j a_j cos(2 pi jk/7) + DIR i sum_j b_j sin(2 pi jk/7) and
-// X[7-k] the same with the sine sum negated (k = 1..3).
-template <int DIR, typename T>
-__device__ __forceinline__ void dft7(cx<T>* v) {
-  // cos and sin of 2 pi m / 7, m = 0..6
-  constexpr double c7[7] = {1.0, 0.6234898018587336, -0.22252093395631434, -0.900968867902419,
-                            -0.900968867902419, -0.22252093395631434, 0.6234898018587336};
-  constexpr double s7[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.43388373911755823,
-                            -0.43388373911755823, -0.9749279121818236, -0.7818314824680298};
-  cx<T> a[4], b[4];
+// cos and sin of 2 pi m / P for the odd radices P = 3, 5, 7 (m = 0..P-1)
+__host__ __device__ constexpr double odd_cos(int P, int m) {
+  const double c3[3] = {1.0, -0.5, -0.5};
+  const double c5[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475,
+                        0.30901699437494745};
+  const double c7[7] = {1.0, 0.6234898018587336, -0.22252093395631434, -0.900968867902419,
+                        -0.900968867902419, -0.22252093395631434, 0.6234898018587336};
+  return P == 3 ? c3[m] : P == 5 ? c5[m] : c7[m];
+}
+__host__ __device__ constexpr double odd_sin(int P, int m) {
+  const double s3[3] = {0.0, 0.8660254037844386, -0.8660254037844386};
+  const double s5[5] = {0.0, 0.9510565162951535, 0.5877852522924731, -0.5877852522924731,
+                        -0.9510565162951535};
+  const double s7[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.43388373911755823,
+                        -0.43388373911755823, -0.9749279121818236, -0.7818314824680298};
+  return P == 3 ? s3[m] : P == 5 ? s5[m] : s7[m];
+}
+
+// Odd prime length P: with a_j = v_j + v_{P-j}, b_j = v_j - v_{P-j}
+// (j = 1..P/2), X[k] = v_0 + sum_j a_j cos(2 pi jk/P) + DIR i sum_j b_j
+// sin(2 pi jk/P) and X[P-k] the same with the sine sum negated.
+template <int P, int DIR, typename T>
+__device__ __forceinline__ void dft_odd(cx<T>* v) {
+  constexpr int H = P / 2;
+  cx<T> a[H + 1], b[H + 1];
 #pragma unroll
-  for (int j = 1; j <= 3; ++j) {
-    a[j] = add(v[j], v[7 - j]);
-    b[j] = sub(v[j], v[7 - j]);
+  for (int j = 1; j <= H; ++j) {
+    a[j] = add(v[j], v[P - j]);
+    b[j] = sub(v[j], v[P - j]);
   }
   const cx<T> x0 = v[0];
-  v[0] = add(add(x0, a[1]), add(a[2], a[3]));
+  cx<T> sum = x0;
 #pragma unroll
-  for (int k = 1; k <= 3; ++k) {
+  for (int j = 1; j <= H; ++j) sum = add(sum, a[j]);
+  v[0] = sum;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
     cx<T> t = x0, u = mk(T(0), T(0));
 #pragma unroll
-    for (int j = 1; j <= 3; ++j) {
-      const int m = (j * k) % 7;
-      t = add(t, scl(a[j], T(c7[m])));
-      u = add(u, scl(b[j], T(s7[m])));
+    for (int j = 1; j <= H; ++j) {
+      const int m = (j * k) % P;
+      t = add(t, scl(a[j], T(odd_cos(P, m))));
+      u = add(u, scl(b[j], T(odd_sin(P, m))));
     }
     const cx<T> ru = rot90<DIR>(u);
     v[k] = add(t, ru);
-    v[7 - k] = sub(t, ru);
+    v[P - k] = sub(t, ru);
   }
+}
+
+// Length 6 = 2 x 3: the 3-point transforms of the even and odd samples,
+// combined with the twiddles exp(DIR 2 pi i k / 6).
+template <int DIR, typename T>
+__device__ __forceinline__ void dft6(cx<T>* v) {
+  cx<T> e[3] = {v[0], v[2], v[4]};
+  cx<T> o[3] = {v[1], v[3], v[5]};
+  dft_odd<3, DIR>(e);
+  dft_odd<3, DIR>(o);
+  const T h = T(0.8660254037844386);   // sin(pi / 3)
+  const cx<T> o1 = mul(o[1], mk(T(0.5), T(DIR) * h));
+  const cx<T> o2 = mul(o[2], mk(T(-0.5), T(DIR) * h));
+  v[0] = add(e[0], o[0]);
+  v[3] = sub(e[0], o[0]);
+  v[1] = add(e[1], o1);
+  v[4] = sub(e[1], o1);
+  v[2] = add(e[2], o2);
+  v[5] = sub(e[2], o2);
 }
 
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dftR(cx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
   else if constexpr (R == 4) dft4<DIR>(v);
-  else if constexpr (R == 7) dft7<DIR>(v);
+  else if constexpr (R == 3 || R == 5 || R == 7) dft_odd<R, DIR>(v);
   else dft8<DIR>(v);
 }
 
@@ -121,20 +157,22 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int m) {
   return DIR < 0 ? w : conj(w);
 }
 
-// Radix plan of a length n = 2^p or 7 * 2^p: an optional leading radix-7
-// stage, then for the power of two 8s, with one 4 (p % 3 == 2) or two 4s
-// (p % 3 == 1); 2 uses a single radix-2 stage.  Encoded as the number of
-// radix-7, radix-2, radix-4 and radix-8 stages.
+// Odd factor of a length n = r * 2^p (r = 1, 3, 5 or 7).
+__host__ __device__ inline int fft_odd_factor(int n) {
+  return n % 7 == 0 ? 7 : n % 5 == 0 ? 5 : n % 3 == 0 ? 3 : 1;
+}
+
+// Radix plan of a length n = r * 2^p: a leading radix-r stage (r = 3, 5, 7),
+// then for the power of two 8s, with one 4 (p % 3 == 2) or two 4s
+// (p % 3 == 1); 2 uses a single radix-2 stage.  Encoded as the odd radix
+// (1: none) and the numbers of radix-2, radix-4 and radix-8 stages.
 struct FftPlan {
-  int n, n4, n8, n2, n7;
+  int n, n4, n8, n2, r;
 };
 
 __host__ __device__ inline FftPlan make_plan(int n) {
-  FftPlan p{n, 0, 0, 0, 0};
-  if (n % 7 == 0) {
-    p.n7 = 1;
-    n /= 7;
-  }
+  FftPlan p{n, 0, 0, 0, fft_odd_factor(n)};
+  n /= p.r;
   int lg = 0;
   while ((1 << lg) < n) ++lg;
   if (lg == 0) return p;
@@ -148,10 +186,11 @@ __host__ __device__ inline FftPlan make_plan(int n) {
 }
 
 // Values per thread that the stages of a length-n plan hold at VPT: a
-// radix-7 stage keeps 7 (VPT/7) values per thread.  Launchers size their
-// blocks with it.
+// radix-r stage (r odd) keeps r (VPT/r) values per thread.  Launchers size
+// their blocks with it.
 __host__ __device__ inline int fft_vpt_cap(int n, int vpt) {
-  return n % 7 == 0 ? 7 * (vpt / 7) : vpt;
+  const int r = fft_odd_factor(n);
+  return r > 1 ? r * (vpt / r) : vpt;
 }
 
 // One in-place Stockham stage of radix R over nseq sequences of length n
@@ -203,16 +242,20 @@ __device__ __forceinline__ void stockham_stage(cx<T>* buf, int n, int Ns, int ns
   __syncthreads();
 }
 
-// Full in-place FFT of nseq sequences of length n = 2^p or 7 * 2^p in LDS.
+// Full in-place FFT of nseq sequences of length n = r * 2^p in LDS; r = 3,
+// 5 or 7 needs ODD (only the set-up transforms see such lengths; without
+// ODD n must be a power of two and no odd-radix stage is compiled in).
 // tw: table of exp(-2 pi i m / twn) with twn a multiple of n.
-template <int DIR, int VPT, typename T>
+template <int DIR, int VPT, bool ODD = false, typename T>
 __device__ void fft_lds(cx<T>* buf, int n, int nseq, int stride, const cx<T>* __restrict__ tw,
                         int twn, int tid, int nthr) {
   const FftPlan p = make_plan(n);
   int Ns = 1;
-  if (p.n7) {
-    stockham_stage<7, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
-    Ns *= 7;
+  if constexpr (ODD) {
+    if (p.r == 3) stockham_stage<3, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    if (p.r == 5) stockham_stage<5, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    if (p.r == 7) stockham_stage<7, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);
+    Ns *= p.r;
   }
   if (p.n2) {
     stockham_stage<2, DIR, VPT>(buf, n, Ns, nseq, stride, tw, twn, tid, nthr);

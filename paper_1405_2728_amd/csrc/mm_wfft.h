@@ -1,5 +1,5 @@
 // Register-resident FFT of one sequence per wavefront (64 lanes), length
-// n = 64 VL with VL in {1, 2, 4, 7, 8}.
+// n = 64 VL with VL in 1..8.
 //
 // Forward, natural input: lane l holds x[l + 64 r] in v[r] (r < VL).
 //   S1  DFT_VL over r, twiddle by W_n^(l k1)            (k1 < VL)
@@ -43,7 +43,8 @@ template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_small(cx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
   else if constexpr (R == 4) dft4<DIR>(v);
-  else if constexpr (R == 7) dft7<DIR>(v);
+  else if constexpr (R == 3 || R == 5 || R == 7) dft_odd<R, DIR>(v);
+  else if constexpr (R == 6) dft6<DIR>(v);
   else if constexpr (R == 8) dft8<DIR>(v);
 }
 

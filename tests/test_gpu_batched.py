@@ -35,11 +35,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-# thin wave-eligible shapes of several groups (one with 448-point transforms),
+# thin wave-eligible shapes of several groups (some with mixed-radix lengths),
 # one Stockham-path shape and one 3-D shape (those two run per sample inside
 # the same sweep)
 SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (20, 10, 1),
-          (10, 8, 6), (260, 130, 1)]   # the last: 448-point x and y transforms
+          (10, 8, 6), (260, 130, 1)]   # the last: 640-point x and 320-point y transforms
 
 
 def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4):

@@ -74,10 +74,14 @@ SHAPES = [
     ((150, 37, 1), (4e-9, 5e-9, 6e-9)),
     ((90, 7, 3), (5e-9, 5e-9, 5e-9)),
     ((300, 5, 1), (5e-9, 5e-9, 5e-9)),
-    # transform length 448 = 7 * 64 (x padded to 896, thin-film y to 448) at
-    # both ends of its range (2n - 1 just above 512 / 256, and exactly 896 / 448)
-    ((260, 129, 1), (5e-9, 5e-9, 5e-9)),
+    # mixed-radix transform lengths 64 VL: VL = 7 at both ends of its range
+    # (x 896, y 448; 2n - 1 just above 768 / 384, and exactly 896 / 448), then
+    # VL = 3 (x 384, y 192), 5 (640, 320) and 6 (768, 384)
+    ((385, 193, 1), (5e-9, 5e-9, 5e-9)),
     ((448, 224, 2), (4e-9, 5e-9, 3e-9)),
+    ((150, 80, 2), (5e-9, 5e-9, 5e-9)),
+    ((290, 140, 1), (4e-9, 5e-9, 6e-9)),
+    ((350, 180, 3), (5e-9, 5e-9, 5e-9)),
 ]
 
 
@@ -127,7 +131,8 @@ def test_heff_ku_map_and_determinism(torch_cuda):
     ctx.close()
 
 
-@pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (100, 50, 2), (260, 129, 2)])
+@pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (100, 50, 2), (260, 129, 2),
+                                   (150, 80, 2), (290, 140, 1)])
 def test_heff_mixed_precision(torch_cuda, shape):
     torch = torch_cuda
     nx, ny, nz = shape
@@ -511,21 +516,22 @@ def test_mixed_without_fp64_reference(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_radix7_padding_matches_powers_of_two(torch_cuda, prec):
-    """The 448-point transforms (x padded to 896, y to 448) and the
-    power-of-two padding (1024, 512) compute the same convolution: fields
-    agree to rounding, and so do the first iterates."""
+@pytest.mark.parametrize("shape", [(300, 150, 2), (150, 80, 1), (400, 200, 1), (350, 180, 1)])
+def test_mixed_radix_padding_matches_powers_of_two(torch_cuda, prec, shape):
+    """Mixed-radix lengths (64 VL with VL = 7, 3, 5, 6) and power-of-two
+    padding compute the same convolution: fields agree to rounding, and so
+    do the first iterates."""
     torch = torch_cuda
     from paper_1405_2728_amd import Context
-    nx, ny, nz = 300, 150, 2
+    nx, ny, nz = shape
     d = (5e-9,) * 3
-    say("case radix-7 padding", prec, (nx, ny, nz))
+    say("case mixed-radix padding", prec, (nx, ny, nz))
     rng = np.random.default_rng(23)
     m0 = synth.uniform_with_noise(synth.tilted(20.0), nx, ny, nz, 0.3, rng)
     out = {}
     for r7 in (1, 0):
         ctx = Context(prec)
-        ctx.set_option("radix7", r7)
+        ctx.set_option("mixed_radix", r7)
         ctx.set_geometry(0, nx, ny, nz, *d)
         ctx.set_material(0, 8e5, 1.3e-11, 500.0, (1, 0, 0))
         ctx.set_field(0, (-1e4, 2e3, 0))
