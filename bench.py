@@ -133,7 +133,7 @@ def stored_traffic(prec, kernel, workload):
     return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
-def run_batched(torch, batched, field_step=10, prec="fp64"):
+def run_batched(torch, batched, field_step=10, prec="fp64", mixed_radix=0, concurrent=1):
     """Sweep the 64 platelets through every field_step-th field of their
     loop; returns (summed iterations, seconds, status)."""
     import synth
@@ -144,10 +144,8 @@ def run_batched(torch, batched, field_step=10, prec="fp64"):
     ctx.set_option("batched", 1 if batched else 0)
     ctx.set_option("use_graph", 1 if batched else 0)
     ctx.set_option("autotune", 1)   # tiles per shape, cached: both runs use the same
-    # power-of-two lengths: the 64 uneven platelets then fall into fewer
-    # launch groups per pass (measured faster for the batched sweep than the
-    # shorter mixed-radix transforms)
-    ctx.set_option("mixed_radix", 0)
+    ctx.set_option("mixed_radix", mixed_radix)
+    ctx.set_option("concurrent_groups", concurrent)
     ms, H = [], []
     for k, p in enumerate(plats):
         ctx.set_geometry(k, *p["n"], *p["d"])

@@ -256,8 +256,13 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * the multiple of 128 >= 2 nx - 1 (up to 1024), the thin-film y length the
  * smaller of the power of two >= 2 ny - 1 and the multiple of 64 (up to
  * 512), so that transforms of 64 VL points with VL = 3, 5, 6, 7 take the
- * place of the next power of two; 0 keeps powers of two).  Unknown keys or
- * values give MM_EINVAL. */
+ * place of the next power of two; 0 keeps powers of two),
+ * "concurrent_groups" (default 1: in batched sweeps the launch groups of a
+ * pass, which touch disjoint samples, run on four auxiliary streams of
+ * default priority forked from and joined back into the context's stream,
+ * as parallel branches of the captured graph; 0 launches them one after
+ * another; results are the same either way).  Unknown keys or values give
+ * MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 
 /* Rows per block of the sample's fused x passes (host int output), as the

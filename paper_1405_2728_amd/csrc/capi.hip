@@ -116,6 +116,12 @@ struct mm_ctx {
   int autotune = 0;             // 1: time the x-pass tiles at mm_set_geometry
   int rows_forced = 0;          // > 0: rows per block of the x passes (tests)
   int mixed_radix = 1;          // 1: wave lengths 64 VL (VL = 3, 5, 6, 7) where shorter
+  int concurrent_groups = 1;    // batched passes: launch groups on forked streams
+  // auxiliary streams (default priority) and fork/join events of the
+  // batched passes, made on first use
+  std::vector<hipStream_t> aux;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
   unsigned prof = 0;            // bit k: time kernel k with events
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -766,18 +772,60 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
   return MM_OK;
 }
 
+// Auxiliary streams for the launch groups of a batched pass.
+constexpr int kAuxStreams = 4;
+
+int ensure_aux(mm_ctx* c) {
+  if (!c->aux.empty()) return MM_OK;
+  for (int k = 0; k < kAuxStreams; ++k) {
+    hipStream_t a = nullptr;
+    hipEvent_t e = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    c->aux.push_back(a);
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->join_ev.push_back(e);
+  }
+  HIPCHK(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  return MM_OK;
+}
+
+// Launch fn(g, stream) for the n groups of one pass.  The groups touch
+// disjoint samples: with concurrent groups they go round-robin to the
+// auxiliary streams, forked from and joined back into the context's stream
+// (under graph capture: parallel branches); otherwise one after another.
+template <typename F>
+void for_groups(mm_ctx* c, int n, F fn) {
+  if (n <= 1 || !c->concurrent_groups || c->aux.empty()) {
+    for (int g = 0; g < n; ++g) fn(g, c->stream);
+    return;
+  }
+  const int K = n < (int)c->aux.size() ? n : (int)c->aux.size();
+  (void)hipEventRecord(c->fork_ev, c->stream);
+  for (int k = 0; k < K; ++k) (void)hipStreamWaitEvent(c->aux[k], c->fork_ev, 0);
+  for (int g = 0; g < n; ++g) fn(g, c->aux[g % K]);
+  for (int k = 0; k < K; ++k) {
+    (void)hipEventRecord(c->join_ev[k], c->aux[k]);
+    (void)hipStreamWaitEvent(c->stream, c->join_ev[k], 0);
+  }
+}
+
 // Reference pass of every batched sample (double precision, same blocks).
 void enqueue_batched_reference(mm_ctx* c, const BatchPlan& P) {
   if (!P.descs_ref) return;
-  hipStream_t st = c->stream;
   Timer t(c, KID_REF);
-  for (const auto& g : P.xg)
+  for_groups(c, (int)P.xg.size(), [&](int i, hipStream_t st) {
+    const auto& g = P.xg[i];
     launch_x_batched<double>(st, false, P.descs_ref, P.items + g.off, g.n, g.a, g.b);
-  for (const auto& g : P.yg)
+  });
+  for_groups(c, (int)P.yg.size(), [&](int i, hipStream_t st) {
+    const auto& g = P.yg[i];
     launch_yz_batched<double>(st, P.descs_ref, P.items + g.off, g.n, g.a, g.b,
                               thin_tensor_stride(g.b, g.a, false));
-  for (const auto& g : P.xg)
+  });
+  for_groups(c, (int)P.xg.size(), [&](int i, hipStream_t st) {
+    const auto& g = P.xg[i];
     launch_x_batched<double>(st, true, P.descs_ref, P.items + g.off, g.n, g.a, g.b);
+  });
 }
 
 // One iteration of every batched sample.
@@ -786,24 +834,27 @@ void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
   const bool sp = single(c);
   {
     Timer t(c, KID_XF);
-    for (const auto& g : P.xg) {
-      if (sp) launch_x_batched<float>(st, false, P.descs, P.items + g.off, g.n, g.a, g.b);
-      else launch_x_batched<double>(st, false, P.descs, P.items + g.off, g.n, g.a, g.b);
-    }
+    for_groups(c, (int)P.xg.size(), [&](int i, hipStream_t s) {
+      const auto& g = P.xg[i];
+      if (sp) launch_x_batched<float>(s, false, P.descs, P.items + g.off, g.n, g.a, g.b);
+      else launch_x_batched<double>(s, false, P.descs, P.items + g.off, g.n, g.a, g.b);
+    });
   }
   {
     Timer t(c, KID_YZ);
-    for (const auto& g : P.yg) {
-      if (sp) launch_yz_batched<float>(st, P.descs, P.items + g.off, g.n, g.a, g.b, g.t);
-      else launch_yz_batched<double>(st, P.descs, P.items + g.off, g.n, g.a, g.b, g.t);
-    }
+    for_groups(c, (int)P.yg.size(), [&](int i, hipStream_t s) {
+      const auto& g = P.yg[i];
+      if (sp) launch_yz_batched<float>(s, P.descs, P.items + g.off, g.n, g.a, g.b, g.t);
+      else launch_yz_batched<double>(s, P.descs, P.items + g.off, g.n, g.a, g.b, g.t);
+    });
   }
   {
     Timer t(c, KID_XIL);
-    for (const auto& g : P.xg) {
-      if (sp) launch_x_batched<float>(st, true, P.descs, P.items + g.off, g.n, g.a, g.b);
-      else launch_x_batched<double>(st, true, P.descs, P.items + g.off, g.n, g.a, g.b);
-    }
+    for_groups(c, (int)P.xg.size(), [&](int i, hipStream_t s) {
+      const auto& g = P.xg[i];
+      if (sp) launch_x_batched<float>(s, true, P.descs, P.items + g.off, g.n, g.a, g.b);
+      else launch_x_batched<double>(s, true, P.descs, P.items + g.off, g.n, g.a, g.b);
+    });
   }
   {
     Timer t(c, KID_FINISH);
@@ -1112,6 +1163,12 @@ void mm_destroy(mm_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto a : c->aux) {
+    (void)hipStreamSynchronize(a);
+    (void)hipStreamDestroy(a);
+  }
+  for (auto e : c->join_ev) (void)hipEventDestroy(e);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   delete c;
 }
 
@@ -1431,6 +1488,13 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     }
     if (plan.members.size() < 2) plan.members.clear();
     for (int k : plan.members) in_batch[k] = 1;
+    if (!plan.members.empty() && c->concurrent_groups) {
+      rc = ensure_aux(c);
+      if (rc != MM_OK) {
+        cleanup();
+        return rc;
+      }
+    }
   }
   // a captured batch of iterations is replayed when the stream allows it
   const bool graph = c->use_graph && c->stream != nullptr && c->prof == 0 && !plan.members.empty();
@@ -1527,6 +1591,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->refine = value != 0.0;
   } else if (!std::strcmp(key, "mixed_radix")) {
     c->mixed_radix = value != 0.0;
+  } else if (!std::strcmp(key, "concurrent_groups")) {
+    c->concurrent_groups = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
   } else if (!std::strcmp(key, "rows_per_block")) {

@@ -42,10 +42,11 @@ SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (
           (10, 8, 6), (260, 130, 1)]   # the last: 640-point x and 320-point y transforms
 
 
-def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4):
+def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent=True):
     from paper_1405_2728_amd import Context
     stream = torch.cuda.Stream() if graph else None
     ctx = Context("mixed" if prec == "mixed_plain" else prec, n_samples=len(shapes), stream=stream)
+    ctx.set_option("concurrent_groups", 1 if concurrent else 0)
     if prec == "mixed_plain":
         ctx.set_option("refine", 0)
     ctx.set_option("batched", 1 if batched else 0)
@@ -158,3 +159,18 @@ def test_minimize_graph_replays_equal_eager(torch_cuda, prec):
         assert a[0] == b[0] and a[1] == b[1]
         assert np.array_equal(a[2], b[2])
     assert all(r[0] > 3 * 16 for r in out[True])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_concurrent_groups_equal_serial(torch_cuda, prec):
+    """Launch groups forked onto auxiliary streams (parallel graph branches)
+    give the same sweep, bit for bit, as groups launched one after another."""
+    torch = torch_cuda
+    say("case concurrent groups", prec)
+    a = run(torch, prec, batched=True, graph=True, concurrent=False)
+    b = run(torch, prec, batched=True, graph=True, concurrent=True)
+    assert a[2] == b[2]
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
