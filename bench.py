@@ -57,8 +57,8 @@ EXTRA_WORKLOADS = ("batched", "adjoint", "loop")
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=400)
-    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--workload", choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS),
                    default="film")
