@@ -1216,8 +1216,10 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   const size_t nspec = (size_t)(s.M + 1) * 3 * nz * ny;
   const size_t nB = full ? (size_t)(s.M + 1) * s.Py * 3 * nz : 0;
   s.nblk = local_blocks(s.N);
-  // per-block sums: room for one row per block (the smallest tile)
-  const size_t npart = (size_t)(s.nblk > nz * ny ? s.nblk : nz * ny) * kNPartial;
+  // per-block sums: room for one row per block (the smallest tile), and for
+  // the first stage of their reduction
+  const int prow = s.nblk > nz * ny ? s.nblk : nz * ny;
+  const size_t npart = (size_t)(prow + finish_extra_rows(prow)) * kNPartial;
   bool ok = hipMalloc(&s.Tt, nT * creal) == hipSuccess &&
             hipMalloc(&s.spec, nspec * 2 * creal) == hipSuccess &&
             hipMalloc(&s.twx, (size_t)s.Px * 2 * creal) == hipSuccess &&

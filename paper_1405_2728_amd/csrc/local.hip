@@ -48,33 +48,55 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
 constexpr int kFinishThreads = 256;
 constexpr int kFinishRows = 4;
 
+// rows b0, b0 + T, ..., b0 + (kFinishRows - 1) T, those past the end
+// clamped to the last row (dropped again by finish_add)
+__device__ __forceinline__ void finish_load(const double* __restrict__ partials, int nb, int b0,
+                                            double (&x)[kFinishRows][kNPartial]) {
+#pragma unroll
+  for (int u = 0; u < kFinishRows; ++u) {
+    const int b = min(b0 + u * kFinishThreads, nb - 1);
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) x[u][q] = partials[(size_t)b * kNPartial + q];
+  }
+}
+
+// add the loaded rows in row order; rows past the end are dropped by a
+// select, not a branch, so that all the loads stay in flight together
+__device__ __forceinline__ void finish_add(int nb, int b0,
+                                           const double (&x)[kFinishRows][kNPartial],
+                                           double (&v)[kNPartial]) {
+#pragma unroll
+  for (int u = 0; u < kFinishRows; ++u) {
+    const bool ok = b0 + u * kFinishThreads < nb;
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) {
+      const double t = q == kPartMax ? fmax(v[q], x[u][q]) : v[q] + x[u][q];
+      v[q] = ok ? t : v[q];
+    }
+  }
+}
+
 __device__ __forceinline__ void finish_block(const double* __restrict__ partials, int nb,
                                              MinState* __restrict__ st, double Ms, double V) {
   __shared__ double scratch[kNPartial * kFinishThreads / 64];
-  const int dn = st->done;   // read while the sums' loads are in flight
+  double x[kFinishRows][kNPartial];
+  finish_load(partials, nb, threadIdx.x, x);
+  // the state is read while the first rows' loads are in flight
+  const int dn = st->done;
+  const FinishIn f = load_finish_in(st);
   double v[kNPartial] = {};
-  for (int b0 = threadIdx.x; b0 < nb; b0 += kFinishRows * kFinishThreads) {
-    double x[kFinishRows][kNPartial];
-#pragma unroll
-    for (int u = 0; u < kFinishRows; ++u) {
-      const int b = min(b0 + u * kFinishThreads, nb - 1);
-#pragma unroll
-      for (int q = 0; q < kNPartial; ++q) x[u][q] = partials[(size_t)b * kNPartial + q];
-    }
-#pragma unroll
-    for (int u = 0; u < kFinishRows; ++u) {
-      if (b0 + u * kFinishThreads >= nb) break;
-#pragma unroll
-      for (int q = 0; q < kNPartial; ++q)
-        v[q] = q == kPartMax ? fmax(v[q], x[u][q]) : v[q] + x[u][q];
-    }
+  finish_add(nb, threadIdx.x, x, v);
+  for (int b0 = threadIdx.x + kFinishRows * kFinishThreads; b0 < nb;
+       b0 += kFinishRows * kFinishThreads) {
+    finish_load(partials, nb, b0, x);
+    finish_add(nb, b0, x, v);
   }
   if (dn != 0) return;
   bool is_max[kNPartial];
   for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
   block_reduce<kFinishThreads>(v, is_max, scratch);
   if (threadIdx.x != 0) return;
-  finish_decision(st, v, Ms, V);
+  finish_decision(st, f, v, Ms, V);
 }
 
 __global__ void __launch_bounds__(kFinishThreads) k_finish(const double* __restrict__ partials,
@@ -224,8 +246,48 @@ void launch_local(hipStream_t s, const LocalArgs& a) {
   hipLaunchKernelGGL(k_local, dim3(local_blocks(N)), dim3(kLocalThreads), 0, s, a);
 }
 
-void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
+// Many per-block sums (large grids): a first stage in which block b sums
+// rows kFinishThreads b .. kFinishThreads (b + 1) - 1 in the fixed order of
+// block_reduce, writing one row per block to out; the one-block finish then
+// sums those.  Few rows are summed by the finish block directly.
+constexpr int kFinishDirect = 2048;
+
+__global__ void __launch_bounds__(kFinishThreads)
+k_finish_stage1(const double* __restrict__ partials, int nb, double* __restrict__ out,
+                const MinState* __restrict__ st) {
+  __shared__ double scratch[kNPartial * kFinishThreads / 64];
+  const int dn = st->done;   // read while the sums' loads are in flight
+  double v[kNPartial] = {};
+  const int r = blockIdx.x * kFinishThreads + threadIdx.x;
+  if (r < nb) {
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) v[q] = partials[(size_t)r * kNPartial + q];
+  }
+  if (dn != 0) return;
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
+  block_reduce<kFinishThreads>(v, is_max, scratch);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) out[(size_t)blockIdx.x * kNPartial + q] = v[q];
+  }
+}
+
+int finish_extra_rows(int nblocks) {
+  return nblocks > kFinishDirect ? (nblocks + kFinishThreads - 1) / kFinishThreads : 0;
+}
+
+// partials: nblocks rows, followed by room for finish_extra_rows(nblocks) more
+void launch_finish(hipStream_t s, double* partials, int nblocks, MinState* st, double Ms,
                    double V) {
+  if (nblocks > kFinishDirect) {
+    const int nb2 = finish_extra_rows(nblocks);
+    double* out = partials + (size_t)nblocks * kNPartial;
+    hipLaunchKernelGGL(k_finish_stage1, dim3(nb2), dim3(kFinishThreads), 0, s, partials, nblocks,
+                       out, st);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, out, nb2, st, Ms, V);
+    return;
+  }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, nblocks, st, Ms, V);
 }
 

@@ -112,14 +112,39 @@ __device__ __forceinline__ void local_cell(const LocalArgs& a, int i, const doub
   compute_cell(a, i, hd, bb, d, part);
 }
 
-// Stop rule and step size from the reduced sums v (one thread).  Sets
-// done / tau / k / pending; records torque and energy.
-__device__ __forceinline__ void finish_decision(MinState* st, const double v[kNPartial],
-                                                double Ms, double V) {
+// State fields the stop rule and step choice read, loaded together with the
+// per-block sums (one memory round trip before the decision instead of two).
+struct FinishIn {
+  double tau, tol, best_torque;
+  long long k, best_k, max_iter, stall_iters, evals;
+  int mode, sweep;
+};
+
+__device__ __forceinline__ FinishIn load_finish_in(const MinState* st) {
+  FinishIn f;
+  f.tau = st->tau;
+  f.tol = st->tol;
+  f.best_torque = st->best_torque;
+  f.k = st->k;
+  f.best_k = st->best_k;
+  f.max_iter = st->max_iter;
+  f.stall_iters = st->stall_iters;
+  f.evals = st->evals;
+  f.mode = st->mode;
+  f.sweep = st->sweep;
+  return f;
+}
+
+// Stop rule and step size from the reduced sums v (one thread); f holds the
+// state as it was when the sums were taken.  Sets done / tau / k / pending;
+// records torque and energy.
+__device__ __forceinline__ void finish_decision(MinState* st, const FinishIn& f,
+                                                const double v[kNPartial], double Ms, double V) {
   const double c = -kMu0 * Ms * V;
   const double Ed = 0.5 * c * v[3], Eex = 0.5 * c * v[4], Ean = -V * v[5], Ez = c * v[6];
   const double E = Ed + Eex + Ean + Ez;
   const double T = sqrt(v[7]) / Ms;
+  const long long k = f.k;
   st->torque = T;
   st->energy = E;
   st->eterm[0] = Ed;
@@ -129,41 +154,40 @@ __device__ __forceinline__ void finish_decision(MinState* st, const double v[kNP
   st->ss = v[0];
   st->sy = v[1];
   st->yy = v[2];
-  st->last_k = st->k;
+  st->last_k = k;
   st->pending = 0;
-  if (st->mode == 2) return;  // evaluation only
-  st->evals += 1;
+  if (f.mode == 2) return;  // evaluation only
+  st->evals = f.evals + 1;
   if (!isfinite(T) || !isfinite(E)) {
     st->done = -1;
     return;
   }
-  const long long k = st->k;
-  if (st->mode == 0) {
+  if (f.mode == 0) {
     int end = 0;
-    if (T < st->tol) end = 1;
-    else if (k >= st->max_iter) end = 2;
-    else if (st->stall_iters > 0) {
-      if (T < st->best_torque) {
+    if (T < f.tol) end = 1;
+    else if (k >= f.max_iter) end = 2;
+    else if (f.stall_iters > 0) {
+      if (T < f.best_torque) {
         st->best_torque = T;
         st->best_k = k;
-      } else if (k - st->best_k >= st->stall_iters) {
+      } else if (k - f.best_k >= f.stall_iters) {
         end = 3;
       }
     }
     if (end != 0) {
-      if (st->sweep == 0) {
+      if (f.sweep == 0) {
         st->done = end;
       } else {
         // record this field, then continue with the next one from the same m
-        const int f = st->field;
-        for (int c = 0; c < 3; ++c) st->mavg_out[3 * f + c] = v[8 + c] * st->inv_N;
-        st->iters_out[f] = k;
+        const int fi = st->field;
+        for (int q = 0; q < 3; ++q) st->mavg_out[3 * fi + q] = v[8 + q] * st->inv_N;
+        st->iters_out[fi] = k;
         if (end > st->worst) st->worst = end;
-        st->field = f + 1;
-        if (f + 1 >= st->n_fields) {
+        st->field = fi + 1;
+        if (fi + 1 >= st->n_fields) {
           st->done = st->worst;
         } else {
-          for (int c = 0; c < 3; ++c) st->H[c] = st->fields[3 * (f + 1) + c];
+          for (int q = 0; q < 3; ++q) st->H[q] = st->fields[3 * (fi + 1) + q];
           st->k = 0;
           st->tau = st->tau0;
           st->last_tau = st->tau0;
@@ -174,12 +198,14 @@ __device__ __forceinline__ void finish_decision(MinState* st, const double v[kNP
       return;
     }
   }
+  double tau = f.tau;
   if (k > 0) {
     const double ss = v[0], sy = fabs(v[1]), yy = v[2];
     const double cand = (k & 1) ? ss / sy : sy / yy;
-    if (isfinite(cand) && cand > 0.0) st->tau = cand;
+    if (isfinite(cand) && cand > 0.0) tau = cand;
   }
-  st->last_tau = st->tau;
+  st->tau = tau;
+  st->last_tau = tau;
   st->k = k + 1;
   st->pending = 1;
 }

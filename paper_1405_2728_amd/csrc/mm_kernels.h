@@ -184,8 +184,11 @@ constexpr int kNPartial = 11;
 constexpr int kPartMax = 7;
 int local_blocks(int N);
 void launch_local(hipStream_t s, const LocalArgs& a);
-void launch_finish(hipStream_t s, const double* partials, int nblocks, MinState* st, double Ms,
+// reduction of the per-block sums, stop rule and step choice; partials has
+// room for finish_extra_rows(nblocks) rows after the nblocks rows
+void launch_finish(hipStream_t s, double* partials, int nblocks, MinState* st, double Ms,
                    double V);
+int finish_extra_rows(int nblocks);
 void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
                    const MinState* st);
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,

@@ -353,14 +353,27 @@ def test_heff_mixed_precision_3d(torch_cuda, shape):
     ctx.close()
 
 
-def test_iterates_match_oracle_3d(torch_cuda):
+# (6, 64, 40) with one row per block: 2560 per-block sums, more than the
+# one-block finish takes directly, so they go through the two-stage reduction
+@pytest.mark.parametrize("shape,rows", [((10, 7, 12), 0), ((6, 64, 40), 1)])
+def test_iterates_match_oracle_3d(torch_cuda, shape, rows):
+    from paper_1405_2728_amd import Context
     torch = torch_cuda
-    nx, ny, nz = 10, 7, 12
+    nx, ny, nz = shape
     d = (3e-9,) * 3
-    say("case iterates 3-D", (nx, ny, nz))
+    say("case iterates 3-D", (nx, ny, nz), "rows per block", rows)
     rng = np.random.default_rng(13)
     m0 = synth.uniform_with_noise((0.3, 0.2, 1.0), nx, ny, nz, 0.05, rng)
-    ctx, P = make(torch, "fp64", nx, ny, nz, d, Ku=5e4, u=(0, 0, 1), H=(2e4, 0.0, 3e4))
+    Ku, u, H = 5e4, (0, 0, 1), (2e4, 0.0, 3e4)
+    ctx = Context("fp64")
+    if rows:
+        ctx.set_option("rows_per_block", rows)
+    ctx.set_geometry(0, nx, ny, nz, *d)
+    ctx.set_material(0, 8e5, 1.3e-11, Ku, u)
+    ctx.set_field(0, H)
+    if rows:
+        assert ctx.rows_per_block(0) == rows
+    P = of.Problem(nx, ny, nz, *d, Ms=8e5, A=1.3e-11, Ku=Ku, u=u, H_ext=H)
     m = torch.tensor(m0, device="cuda")
     ref = om.minimize(P, m0, tol=0.0, max_iter=10, record=True)
     for k in range(10):
