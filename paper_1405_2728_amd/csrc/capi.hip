@@ -775,17 +775,32 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
 // Auxiliary streams for the launch groups of a batched pass.
 constexpr int kAuxStreams = 4;
 
+// All or nothing: on a failure the handles made so far are destroyed and the
+// batched passes keep launching their groups one after another.
 int ensure_aux(mm_ctx* c) {
   if (!c->aux.empty()) return MM_OK;
-  for (int k = 0; k < kAuxStreams; ++k) {
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int k = 0; k < kAuxStreams && e == hipSuccess; ++k) {
     hipStream_t a = nullptr;
-    hipEvent_t e = nullptr;
-    HIPCHK(c, hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
-    c->aux.push_back(a);
-    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    c->join_ev.push_back(e);
+    hipEvent_t j = nullptr;
+    e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    aux.push_back(a);
+    e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+    if (e == hipSuccess) join.push_back(j);
   }
-  HIPCHK(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  if (e != hipSuccess) {
+    for (auto a : aux) (void)hipStreamDestroy(a);
+    for (auto j : join) (void)hipEventDestroy(j);
+    if (fork) (void)hipEventDestroy(fork);
+    return fail(c, MM_EHIP, std::string("auxiliary streams: ") + hipGetErrorString(e));
+  }
+  c->aux = aux;
+  c->join_ev = join;
+  c->fork_ev = fork;
   return MM_OK;
 }
 
@@ -1462,6 +1477,15 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     dfree(mavg);
     dfree(its);
   };
+  // a failed HIP call frees the sweep's tables before it returns
+#define SWEEP_CHK(expr)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      cleanup();                                                                 \
+      return fail(c, MM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                            \
+  } while (0)
   if (hipMalloc((void**)&fields, nf3 * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&mavg, nf3 * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&its, (size_t)S * n_fields * sizeof(long long)) != hipSuccess) {
@@ -1469,7 +1493,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     (void)hipGetLastError();
     return fail(c, MM_ENOMEM, "device allocation for the sweep tables failed");
   }
-  HIPCHK(c, hipMemcpyAsync(fields, H, nf3 * sizeof(double), hipMemcpyHostToDevice, st));
+  SWEEP_CHK(hipMemcpyAsync(fields, H, nf3 * sizeof(double), hipMemcpyHostToDevice, st));
   // every sample runs its whole field list on the device; the host polls
   for (int k = 0; k < S; ++k) {
     Sample& s = c->smp[k];
@@ -1524,7 +1548,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
             return fail(c, MM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
           }
         }
-        HIPCHK(c, hipGraphLaunch(plan.graph, c->stream));
+        SWEEP_CHK(hipGraphLaunch(plan.graph, c->stream));
       } else {
         enqueue_batched_reference(c, plan);
         for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
@@ -1554,8 +1578,8 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
       }
   }
   std::vector<long long> ih((size_t)S * n_fields);
-  HIPCHK(c, hipMemcpyAsync(m_avg, mavg, nf3 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipMemcpyAsync(ih.data(), its, ih.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+  SWEEP_CHK(hipMemcpyAsync(m_avg, mavg, nf3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  SWEEP_CHK(hipMemcpyAsync(ih.data(), its, ih.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
   cleanup();
   int worst = MM_OK;
   for (int k = 0; k < S; ++k) {
@@ -1572,6 +1596,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     for (size_t q = 0; q < ih.size(); ++q) iters[q] = ih[q];
   return worst;
 }
+#undef SWEEP_CHK
 
 int mm_set_option(mm_ctx* c, const char* key, double value) {
   if (!c || !key) return MM_EINVAL;
