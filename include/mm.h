@@ -275,7 +275,9 @@ int mm_rows_per_block(mm_ctx* ctx, int sample, int* rows);
 int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
 
 /* Whether this build's kernels handle a grid (1) or not (0) with the
- * automatic demag path (and the default "mixed_radix" padding): nx <= 8192;
+ * automatic demag path (and the default "mixed_radix" padding): nx <= 2048
+ * (the fused x passes hold a row's three components, 3 Px/2 complex values,
+ * in one block);
  * nz <= 4 with 2ny-1 padded (to a power of two or a multiple of 64) so that
  * 3 nz Py complex values fit one block, or nz > 4 with ny, nz <= 256 (y and
  * z padded to powers of two in 64..512). */

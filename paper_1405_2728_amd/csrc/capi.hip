@@ -173,7 +173,10 @@ int pad_3d(int n) {
 int choose_path(int prec, int pref, int nx, int ny, int nz, bool mr = true) {
   if (nx < 1 || ny < 1 || nz < 1) return PATH_NONE;
   if (nx > (1 << 14) || ny > (1 << 13)) return PATH_NONE;
-  if (pad_x(nx, mr) / 2 > 8192) return PATH_NONE;
+  // the fused x passes hold the three components of a row in one block:
+  // 3 M complex values within 512 threads x 16 values and the LDS
+  const long long xv = 3LL * (pad_x(nx, mr) / 2);
+  if (xv > 512LL * 16 || xv * (prec == MM_MIXED ? 8 : 16) > 160LL * 1024) return PATH_NONE;
   const bool thin_ok = yz_thin_fits(nz, pad_thin_y(ny, mr), prec == MM_MIXED);
   const bool full_ok = full3d_len_ok(pad_3d(ny)) && full3d_len_ok(pad_3d(nz));
   if (pref == 1) return thin_ok ? PATH_THIN : PATH_NONE;

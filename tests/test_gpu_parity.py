@@ -82,6 +82,9 @@ SHAPES = [
     ((150, 80, 2), (5e-9, 5e-9, 5e-9)),
     ((290, 140, 1), (4e-9, 5e-9, 6e-9)),
     ((350, 180, 3), (5e-9, 5e-9, 5e-9)),
+    # LDS-FFT x passes beyond the wave lengths, up to the longest rows (Px 4096)
+    ((1100, 4, 2), (5e-9, 5e-9, 5e-9)),
+    ((2048, 3, 1), (5e-9, 5e-9, 5e-9)),
 ]
 
 
@@ -132,7 +135,7 @@ def test_heff_ku_map_and_determinism(torch_cuda):
 
 
 @pytest.mark.parametrize("shape", [(32, 16, 1), (33, 17, 4), (100, 50, 2), (260, 129, 2),
-                                   (150, 80, 2), (290, 140, 1)])
+                                   (150, 80, 2), (290, 140, 1), (2048, 3, 1)])
 def test_heff_mixed_precision(torch_cuda, shape):
     torch = torch_cuda
     nx, ny, nz = shape

@@ -54,6 +54,12 @@ def test_support_predicate(lib):
     assert lib.mm_supported(0, 128, 128, 128) == 1
     assert lib.mm_supported(1, 128, 128, 128) == 1
     assert lib.mm_supported(0, 1, 1, 5) == 1
+    # longest x rows: 3 Px/2 complex values of a row must fit one block
+    for prec in (0, 1):
+        assert lib.mm_supported(prec, 2048, 3, 1) == 1     # Px 4096
+        assert lib.mm_supported(prec, 2049, 3, 1) == 0     # Px 8192
+        assert lib.mm_supported(prec, 2048, 8, 8) == 1     # 3-D path, same x passes
+        assert lib.mm_supported(prec, 2049, 8, 8) == 0
     assert lib.mm_supported(0, 300, 256, 256) == 1
     assert lib.mm_supported(0, 8, 257, 8) == 0
     assert lib.mm_supported(0, 8, 8, 257) == 0
