@@ -67,6 +67,9 @@ def parse():
                    help="with --quick: also time the run with captured HIP graphs")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-iters", type=int, default=20)
+    p.add_argument("--bb-switch", type=float, default=0.0, metavar="KAPPA",
+                   help="with --workload loop: step choice (0 alternation of eq. (12); "
+                        "kappa > 0 the ratio switch tau2 if tau2 < kappa tau1)")
     p.add_argument("--quick", action="store_true",
                    help="only the timed run (for profilers): no profiled pass, no other "
                         "precision, no CPU baseline")
@@ -193,12 +196,13 @@ def run_adjoint(torch):
             "dJ_dA": g["A"], "dJ_dMs": g["Ms"], "status": [int(rc), int(rc2)]}
 
 
-def run_loop(torch, prec, n, d, m0, fields, tol=1e-6):
+def run_loop(torch, prec, n, d, m0, fields, tol=1e-6, bb_switch=0.0):
     """One device-driven sweep over the whole loop; (evaluations, seconds,
-    <m> per field, status)."""
+    <m> per field, status).  bb_switch: the library's step-choice option."""
     import synth
     from paper_1405_2728_amd import Context
     ctx = Context(prec)
+    ctx.set_option("bb_switch", bb_switch)
     ctx.set_geometry(0, *n, *d)
     ctx.set_material(0, synth.PERMALLOY["Ms"], synth.PERMALLOY["A"], synth.PERMALLOY["Ku"],
                      synth.PERMALLOY["u"])
@@ -223,13 +227,14 @@ def coercive_fields_mT(mavg, fields, h):
     return [None if v is None else float(v) for v in (down, up)]
 
 
-def loops(torch):
+def loops(torch, bb_switch=0.0):
     import synth
     out = {}
     w = synth.workload(1)
     h = synth.tilted(1.0)
     for prec in ("fp64", "mixed"):
-        ev, dt, mavg, rc = run_loop(torch, prec, w["n"], w["d"], w["m0"], w["fields"])
+        ev, dt, mavg, rc = run_loop(torch, prec, w["n"], w["d"], w["m0"], w["fields"],
+                                    bb_switch=bb_switch)
         out["film400x200x4_" + prec] = {"evals_per_loop": ev, "seconds": dt, "evals_per_s": ev / dt,
                                         "coercive_mT": coercive_fields_mT(mavg, w["fields"], h),
                                         "status": rc}
@@ -250,7 +255,7 @@ def loops(torch):
         hh = synth.tilted(deg)
         m0 = synth.uniform_with_noise(hh, *n, 1e-3, rng)
         f = synth.loop_fields(50.0, step, hh)
-        ev, dt, mavg, rc = run_loop(torch, "fp64", n, (dd,) * 3, m0, f)
+        ev, dt, mavg, rc = run_loop(torch, "fp64", n, (dd,) * 3, m0, f, bb_switch=bb_switch)
         out[name] = {"fields": len(f), "evals_per_loop": ev, "evals_per_field": ev / len(f),
                      "seconds": dt, "coercive_mT": coercive_fields_mT(mavg, f, hh), "status": rc}
         print(name, out[name], file=sys.stderr, flush=True)
@@ -300,10 +305,10 @@ def main():
                           "speedup": (ib / tb) / (iseq / tseq), "status": [rcb, rcs]}))
         return
     if a.workload == "loop":
-        r = loops(torch)
+        r = loops(torch, a.bb_switch)
         print(json.dumps({"metric": "H_eff evaluations and seconds per hysteresis loop "
                                     "(201 fields)", "n_gpus": 1, "data": "synthetic",
-                          "loops": r}))
+                          "bb_switch": a.bb_switch, "loops": r}))
         return
     if a.workload == "adjoint":
         r = run_adjoint(torch)

@@ -228,7 +228,13 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
 /* Options (numeric): "tau0" (m/A; 0 = 1e-3/Ms), "poll_every" (iterations
  * between host checks of the stop flag, default 32), "stall_iters" (mixed
  * form without defect correction: iterations without a new torque minimum
- * before MM_STALLED, default 500; 0 disables), "use_graph" (1, with a
+ * before MM_STALLED, default 500; 0 disables), "bb_switch" (step choice,
+ * taken at each reset of the minimiser state: 0, the default, alternates
+ * the two steps of eq. (12) by the parity of k as Sec. 2 does; kappa > 0
+ * takes tau2 = |s.y|/y.y where tau2 < kappa tau1, else tau1 = s.s/|s.y|,
+ * a ratio switch between the two steps in the spirit of the more elaborate
+ * switching Sec. 2 attributes to Exl et al.; must be finite and >= 0),
+ * "use_graph" (1, with a
  * non-null stream: mm_minimize_to_tol and mm_hysteresis_sweep replay each
  * batch of poll_every iterations after the first as one captured HIP graph;
  * mm_minimize_to_tol keeps its graph per sample while m, poll_every, the

@@ -36,6 +36,13 @@ R8  Renormalisation after every update (eq. (7) preserves |m| exactly; this
 R9  Each field of a sweep restarts the BB state (k = 0, tau = tau0) from the
     previous field's magnetisation (Sec. 4: the previous configuration is
     the starting point).
+R10 Step switch (optional, bb_switch = kappa > 0).  Sec. 2 contrasts its
+    plain alternation with a more elaborate switch between the two steps
+    used by Exl et al., without stating it.  The switch offered here is the
+    ratio rule of adaptive BB methods: tau2 where tau2 < kappa tau1, else
+    tau1, each formed with |s.y| and guarded as in R5.  Since
+    (s.y)^2 <= (s.s)(y.y), tau2 <= tau1: kappa > 1 always takes tau2, a
+    tiny kappa always tau1.  Parity unpinned against Exl et al.'s own rule.
 """
 
 import numpy as np
@@ -88,14 +95,18 @@ def normalise(m):
     return m / np.sqrt(np.sum(m * m, axis=0))[None]
 
 
-def bb_candidate(k, ss, sy, yy):
-    """Step size of eq. (12) for iteration k >= 1 (readings R4, R5);
-    returns None when the guard rejects the candidate."""
+def bb_candidate(k, ss, sy, yy, bb_switch=0.0):
+    """Step size of eq. (12) for iteration k >= 1 (readings R4, R5; with
+    bb_switch > 0 the ratio switch of reading R10); returns None when the
+    guard rejects the candidate."""
     with np.errstate(divide="ignore", invalid="ignore"):
-        if k % 2 == 1:
-            cand = ss / abs(sy) if sy != 0 else np.inf
+        ss, sy, yy = np.float64(ss), np.float64(abs(sy)), np.float64(yy)
+        tau1 = ss / sy
+        tau2 = sy / yy
+        if bb_switch > 0:
+            cand = tau2 if tau2 < bb_switch * tau1 else tau1
         else:
-            cand = abs(sy) / yy if yy != 0 else np.inf
+            cand = tau1 if k % 2 == 1 else tau2
     if not np.isfinite(cand) or cand <= 0:
         return None
     return float(cand)
@@ -106,7 +117,7 @@ def default_tau0(Ms):
     return 1e-3 / Ms
 
 
-def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False):
+def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb_switch=0.0):
     """Relax m0 with the BB midpoint scheme until the torque is below tol.
 
     Returns a dict with the final m, the number of updates ``iters``, the
@@ -137,7 +148,7 @@ def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False):
             s = m - m_prev
             y = g - g_prev
             cand = bb_candidate(k, float(np.sum(s * s)), float(np.sum(s * y)),
-                                float(np.sum(y * y)))
+                                float(np.sum(y * y)), bb_switch)
             if cand is not None:
                 tau = cand
         if record:
@@ -147,7 +158,7 @@ def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False):
         k += 1
 
 
-def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None):
+def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0.0):
     """Warm-started hysteresis sweep (Sec. 4, reading R9).
 
     ``fields`` is [n_fields, 3] in A/m.  For each field the minimiser runs
@@ -164,7 +175,7 @@ def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None):
     states = []
     for f, H in enumerate(fields):
         problem.H_ext = H.copy()
-        res = minimize(problem, m, tol=tol, max_iter=max_iter, tau0=tau0)
+        res = minimize(problem, m, tol=tol, max_iter=max_iter, tau0=tau0, bb_switch=bb_switch)
         m = res["m"]
         mavg[f] = m.reshape(3, -1).mean(axis=1)
         iters[f] = res["iters"]

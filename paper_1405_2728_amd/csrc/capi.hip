@@ -109,6 +109,7 @@ struct mm_ctx {
   double tau0 = 0.0;
   int poll_every = 32;
   long long stall_iters = 500;
+  double bb_switch = 0.0;       // step choice: 0 alternation of eq. (12); kappa > 0 ratio switch
   int use_graph = 0;
   int batched = 1;              // sweeps of several samples share launches
   int path_pref = 0;            // 0 automatic, 1 thin-film, 2 full 3-D
@@ -1063,7 +1064,7 @@ int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
 
 int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
   launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                     stall_of(c, s), 0, s.H);
+                     stall_of(c, s), 0, s.H, c->bb_switch);
   s.ref_age = kRefStale;
   // full batches after the first replay a captured graph (use_graph on a
   // non-null stream, kernels not being timed); the first batch runs eagerly
@@ -1300,7 +1301,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.has_mat = s.Ms > 0;
   s.evals_total = s.iters_total = 0;
   if (s.has_mat)
-    launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
+    launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1335,7 +1336,7 @@ int mm_set_material(mm_ctx* c, int sample, double Ms, double A, double Ku, const
   s.has_mat = true;
   s.ref_age = kRefStale;   // the reference field scales with Ms
   ++s.mat_version;         // material constants are baked into captured launches
-  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1347,7 +1348,8 @@ int mm_set_field(mm_ctx* c, int sample, const double* H) {
     return fail(c, MM_EINVAL, "field must be three finite numbers");
   Sample& s = c->smp[sample];
   for (int q = 0; q < 3; ++q) s.H[q] = H[q];
-  if (s.has_mat) launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
+  if (s.has_mat)
+    launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1356,7 +1358,7 @@ int mm_reset(mm_ctx* c, int sample) {
   int rc = check_sample(c, sample, true);
   if (rc != MM_OK) return rc;
   Sample& s = c->smp[sample];
-  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H);
+  launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1502,7 +1504,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     Sample& s = c->smp[k];
     for (int q = 0; q < 3; ++q) s.H[q] = H[((size_t)k * n_fields) * 3 + q];
     launch_reset_state(st, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                       stall_of(c, s), 0, s.H);
+                       stall_of(c, s), 0, s.H, c->bb_switch);
     launch_sweep_start(st, s.st, fields + (size_t)k * n_fields * 3, n_fields,
                        mavg + (size_t)k * n_fields * 3, its + (size_t)k * n_fields, 1.0 / s.N);
     s.ref_age = kRefStale;
@@ -1610,6 +1612,10 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
   } else if (!std::strcmp(key, "poll_every")) {
     if (value < 1 || value > 100000) return fail(c, MM_EINVAL, "poll_every out of range");
     c->poll_every = (int)value;
+  } else if (!std::strcmp(key, "bb_switch")) {
+    if (!(value >= 0.0) || !std::isfinite(value))
+      return fail(c, MM_EINVAL, "bb_switch must be finite and >= 0");
+    c->bb_switch = value;
   } else if (!std::strcmp(key, "stall_iters")) {
     if (value < 0) return fail(c, MM_EINVAL, "stall_iters must be >= 0");
     c->stall_iters = (long long)value;

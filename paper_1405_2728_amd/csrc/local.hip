@@ -164,7 +164,8 @@ __global__ void __launch_bounds__(256) k_mean_finish(const double* __restrict__ 
 }
 
 __global__ void k_reset_state(MinState* st, double tau0, double tol, long long max_iter,
-                              long long stall_iters, int mode, double hx, double hy, double hz) {
+                              long long stall_iters, int mode, double hx, double hy, double hz,
+                              double bb_switch) {
   MinState z;
   z.tau = tau0;
   z.torque = 0.0;
@@ -195,6 +196,7 @@ __global__ void k_reset_state(MinState* st, double tau0, double tol, long long m
   z.iters_out = nullptr;
   z.worst = 1;
   z.inv_N = 0.0;
+  z.bb_switch = bb_switch;
   *st = z;
 }
 
@@ -220,9 +222,9 @@ __global__ void k_set_mode(MinState* st, int mode) {
 }
 
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
-                        long long stall_iters, int mode, const double H[3]) {
+                        long long stall_iters, int mode, const double H[3], double bb_switch) {
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(1), 0, s, st, tau0, tol, max_iter, stall_iters,
-                     mode, H[0], H[1], H[2]);
+                     mode, H[0], H[1], H[2], bb_switch);
 }
 
 void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,

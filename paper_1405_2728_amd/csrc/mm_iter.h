@@ -118,6 +118,7 @@ struct FinishIn {
   double tau, tol, best_torque;
   long long k, best_k, max_iter, stall_iters, evals;
   int mode, sweep;
+  double bb_switch;
 };
 
 __device__ __forceinline__ FinishIn load_finish_in(const MinState* st) {
@@ -132,6 +133,7 @@ __device__ __forceinline__ FinishIn load_finish_in(const MinState* st) {
   f.evals = st->evals;
   f.mode = st->mode;
   f.sweep = st->sweep;
+  f.bb_switch = st->bb_switch;
   return f;
 }
 
@@ -200,8 +202,11 @@ __device__ __forceinline__ void finish_decision(MinState* st, const FinishIn& f,
   }
   double tau = f.tau;
   if (k > 0) {
+    // eq. (12): tau1 = s.s / |s.y|, tau2 = |s.y| / y.y; alternately by the
+    // parity of k, or (bb_switch = kappa > 0) tau2 where tau2 < kappa tau1
     const double ss = v[0], sy = fabs(v[1]), yy = v[2];
-    const double cand = (k & 1) ? ss / sy : sy / yy;
+    const double t1 = ss / sy, t2 = sy / yy;
+    const double cand = f.bb_switch > 0.0 ? (t2 < f.bb_switch * t1 ? t2 : t1) : ((k & 1) ? t1 : t2);
     if (isfinite(cand) && cand > 0.0) tau = cand;
   }
   st->tau = tau;

@@ -42,6 +42,10 @@ struct MinState {
   long long* iters_out;    // device [n_fields]
   int worst;               // 1 converged, 2 max_iter, 3 stalled (worst so far)
   double inv_N;            // 1 / cells, for the mean
+  // Step choice: 0 alternates the two steps of eq. (12) by the parity of k;
+  // kappa > 0 takes the short step tau2 where tau2 < kappa tau1, else tau1
+  // (a ratio switch between the two steps)
+  double bb_switch;
 };
 
 // Conjugate-gradient state of an adjoint solve, resident in device memory.
@@ -192,7 +196,8 @@ int finish_extra_rows(int nblocks);
 void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
                    const MinState* st);
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
-                        long long stall_iters, int mode, const double H[3]);
+                        long long stall_iters, int mode, const double H[3],
+                        double bb_switch = 0.0);
 void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,
                         double* mavg_out, long long* iters_out, double inv_N);
 void launch_set_mode(hipStream_t s, MinState* st, int mode);

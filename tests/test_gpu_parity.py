@@ -186,6 +186,48 @@ def test_iterates_match_oracle(torch_cuda, start, tol_m, tol_tau):
     ctx.close()
 
 
+def test_bb_switch_matches_oracle(torch_cuda):
+    """Option bb_switch (the ratio switch between the two steps of eq. (12)):
+    the first iterates and a run to tolerance follow the oracle's rule."""
+    from paper_1405_2728_amd import Context
+    torch = torch_cuda
+    nx, ny, nz = 20, 12, 2
+    d = (5e-9,) * 3
+    kappa = 0.5
+    say("case bb_switch", (nx, ny, nz), kappa)
+    rng = np.random.default_rng(11)
+    m0 = synth.uniform_with_noise((1, 0.2, 0), nx, ny, nz, 0.05, rng)
+    H = (2e4, 3e3, 0.0)
+    P = of.Problem(nx, ny, nz, *d, Ms=8e5, A=1.3e-11, Ku=500.0, u=(1, 0, 0), H_ext=H)
+    ctx = Context("fp64")
+    ctx.set_option("bb_switch", kappa)
+    ctx.set_geometry(0, nx, ny, nz, *d)
+    ctx.set_material(0, 8e5, 1.3e-11, 500.0, (1, 0, 0))
+    ctx.set_field(0, H)
+    m = torch.tensor(m0, device="cuda")
+    ref = om.minimize(P, m0, tol=0.0, max_iter=15, record=True, bb_switch=kappa)
+    alt = om.minimize(P, m0, tol=0.0, max_iter=15, record=True)
+    assert not np.array_equal(ref["taus"], alt["taus"])     # the switch is in effect
+    taus = []
+    for k in range(15):
+        info = ctx.minimize_step(0, m)
+        taus.append(info["tau"])
+        assert abs(info["torque"] - ref["torques"][k]) < 1e-9 * ref["torques"][k]
+    err = np.max(np.abs(m.cpu().numpy() - ref["m"]))
+    tau_err = np.max(np.abs(np.array(taus) / np.array(ref["taus"]) - 1))
+    say("  15-iterate max diff", err, "tau rel", tau_err)
+    assert err < 1e-11 and tau_err < 1e-9
+    m = torch.tensor(m0, device="cuda")
+    r = ctx.minimize_to_tol(0, m, tol=1e-7, max_iter=100000)
+    full = om.minimize(P, m0, tol=1e-7, bb_switch=kappa)
+    say("  iters gpu", r["iters"], "oracle", full["iters"], "alternation",
+        om.minimize(P, m0, tol=1e-7)["iters"])
+    assert r["converged"] and full["converged"]
+    assert np.max(np.abs(m.cpu().numpy() - full["m"])) < 1e-4
+    assert abs(r["energy"] - full["energy"]) < 1e-9 * abs(full["energy"])
+    ctx.close()
+
+
 def test_minimize_to_tol_cross_stationary(torch_cuda):
     torch = torch_cuda
     nx, ny, nz = 16, 8, 1

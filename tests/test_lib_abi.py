@@ -109,6 +109,10 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"mixed_radix", 1.0) == 0
         assert lib.mm_set_option(h, b"concurrent_groups", 0.0) == 0
         assert lib.mm_set_option(h, b"concurrent_groups", 1.0) == 0
+        assert lib.mm_set_option(h, b"bb_switch", -0.5) == -1
+        assert lib.mm_set_option(h, b"bb_switch", float("inf")) == -1
+        assert lib.mm_set_option(h, b"bb_switch", 0.5) == 0
+        assert lib.mm_set_option(h, b"bb_switch", 0.0) == 0
         assert lib.mm_set_option(h, b"rows_per_block", -1.0) == -1
         assert lib.mm_set_option(h, b"rows_per_block", 2.5) == -1
         assert lib.mm_set_option(h, b"rows_per_block", 3.0) == 0

@@ -240,6 +240,53 @@ def test_bb_guard_rejects_degenerate_candidates():
     assert mz.bb_candidate(2, 2.0, -4.0, 8.0) == 0.5
 
 
+def test_bb_switch_picks_by_ratio():
+    """Reading R10: tau1 = s.s/|s.y| = 2, tau2 = |s.y|/y.y = 1 (ratio 1/2);
+    the switch ignores the parity of k."""
+    for k in (1, 2):
+        assert mz.bb_candidate(k, 4.0, -2.0, 2.0, bb_switch=0.4) == 2.0
+        assert mz.bb_candidate(k, 4.0, -2.0, 2.0, bb_switch=0.6) == 1.0
+        assert mz.bb_candidate(k, 1.0, 0.0, 1.0, bb_switch=0.5) is None   # tau2 = 0
+        assert mz.bb_candidate(k, 0.0, 0.0, 0.0, bb_switch=0.5) is None
+    # without the switch, the parity decides
+    assert mz.bb_candidate(1, 4.0, -2.0, 2.0) == 2.0
+    assert mz.bb_candidate(2, 4.0, -2.0, 2.0) == 1.0
+
+
+def test_bb_switch_extremes_on_random_sums():
+    """kappa > 1 always takes the short step and a tiny kappa the long one:
+    tau2 <= tau1 by Cauchy-Schwarz, and tau1 tau2 = s.s / y.y."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        s_, y_ = rng.standard_normal(12), rng.standard_normal(12)
+        ss, sy, yy = float(s_ @ s_), float(s_ @ y_), float(y_ @ y_)
+        short = mz.bb_candidate(1, ss, sy, yy, bb_switch=2.0)
+        long_ = mz.bb_candidate(2, ss, sy, yy, bb_switch=1e-300)
+        assert short <= long_
+        assert abs(short * long_ - ss / yy) <= 1e-14 * ss / yy
+        assert mz.bb_candidate(2, ss, sy, yy) == short       # alternation, even k
+        assert mz.bb_candidate(1, ss, sy, yy) == long_       # odd k
+
+
+def test_bb_switch_reaches_the_same_minimum():
+    """The ratio switch (and its short-step extreme) is a descent to the
+    same stationary point as the alternation from the same start (four
+    cells, the general-optimiser case above).  Long steps alone (tiny
+    kappa) need not converge without a safeguard and are not run here."""
+    P = fields.Problem(2, 2, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=5e4,
+                       u=(0.0, 0.6, 0.8), H_ext=(3e4, -1e4, 2e4), demag="direct")
+    m0 = random_unit((1, 2, 2), 8)
+    ref = mz.minimize(P, m0, tol=1e-11, record=True)
+    assert ref["converged"]
+    for kappa in (0.5, 2.0):
+        r = mz.minimize(P, m0, tol=1e-11, record=True, bb_switch=kappa)
+        assert r["converged"], kappa
+        assert np.max(np.abs(r["m"] - ref["m"])) < 1e-8, kappa
+        assert abs(r["energy"] - ref["energy"]) < 1e-12 * abs(ref["energy"]), kappa
+        n = min(len(r["taus"]), len(ref["taus"]))
+        assert not np.array_equal(r["taus"][:n], ref["taus"][:n]), kappa
+
+
 def test_converged_start_takes_no_step_and_max_iter_caps():
     P = fields.Problem(1, 1, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=0.0, Ku=500.0,
                        H_ext=(1e4, 0.0, 0.0))
