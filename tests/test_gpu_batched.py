@@ -42,7 +42,8 @@ SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (
           (10, 8, 6), (260, 130, 1)]   # the last: 640-point x and 320-point y transforms
 
 
-def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent=True):
+def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent=True,
+        bb_switch=0.0):
     from paper_1405_2728_amd import Context
     stream = torch.cuda.Stream() if graph else None
     ctx = Context("mixed" if prec == "mixed_plain" else prec, n_samples=len(shapes), stream=stream)
@@ -52,6 +53,7 @@ def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent
     ctx.set_option("batched", 1 if batched else 0)
     ctx.set_option("use_graph", 1 if graph else 0)
     ctx.set_option("poll_every", 8)
+    ctx.set_option("bb_switch", bb_switch)
     rng = np.random.default_rng(31)
     ms, H = [], []
     for k, n in enumerate(shapes):
@@ -87,6 +89,23 @@ def test_batched_equals_per_sample(torch_cuda, prec):
     assert np.array_equal(a[0], b[0])
     for x, y in zip(a[3], b[3]):
         assert np.array_equal(x, y)
+
+
+def test_batched_equals_per_sample_with_bb_switch(torch_cuda):
+    """The step switch lives in the shared finish step: the batched sweep
+    (one finish launch for all samples) matches the per-sample one bitwise."""
+    torch = torch_cuda
+    say("case batched vs per-sample, bb_switch 0.5")
+    a = run(torch, "fp64", batched=False, shapes=SHAPES[:5], bb_switch=0.5)
+    b = run(torch, "fp64", batched=True, shapes=SHAPES[:5], bb_switch=0.5)
+    c = run(torch, "fp64", batched=True, shapes=SHAPES[:5])
+    say("  iterations", b[1].tolist(), "alternation", c[1].tolist(), "status", a[2], b[2])
+    assert a[2] == b[2]
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
+    assert not np.array_equal(b[1], c[1])        # the switch is in effect
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
