@@ -1088,6 +1088,10 @@ int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm
     if (rc != MM_OK) return rc;
     prof_collect(c);
     if (s.st_host->done != 0) break;
+    // the evaluation that reaches max_iter ends the run on the device; a
+    // state that still runs well after it would keep the host polling
+    if (left < -(long long)c->poll_every)
+      return fail(c, MM_ESTATE, "the device state did not end the run at max_iter");
   }
   const MinState& h = *s.st_host;
   s.evals_total += h.evals;

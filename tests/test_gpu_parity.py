@@ -468,6 +468,14 @@ def test_error_paths(torch_cuda):
     with pytest.raises(MMError) as ei:
         ctx.set_geometry(0, 8, 300, 8, 1e-9, 1e-9, 1e-9)      # y padding 1024 in 3-D
     assert ei.value.code == -6
+    with pytest.raises(MMError) as ei:
+        ctx.set_geometry(0, 2049, 2, 1, 1e-9, 1e-9, 1e-9)     # x rows beyond Px 4096
+    assert ei.value.code == -6
+    for bad in ((0, 4, 1, 1e-9, 1e-9, 1e-9), (4, 4, 1, -1e-9, 1e-9, 1e-9),
+                (4, 4, 1, 1e-9, float("nan"), 1e-9)):
+        with pytest.raises(MMError) as ei:
+            ctx.set_geometry(0, *bad)                          # empty grid, bad cell
+        assert ei.value.code == -1
     ctx.set_option("demag_path", 1)
     with pytest.raises(MMError) as ei:
         ctx.set_geometry(0, 8, 8, 8, 1e-9, 1e-9, 1e-9)        # thin path: at most 4 layers
