@@ -289,6 +289,14 @@ int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
  * z padded to powers of two in 64..512). */
 int mm_supported(int prec, int nx, int ny, int nz);
 
+/* State of the sample's minimiser after its most recent call (host *info;
+ * synchronises): tau = the step of the most recent update of eq. (7) (tau0
+ * before the first), torque and energy of the most recent evaluation m_k
+ * (Sec. 2 stop quantity max|g_k|/Ms and U(m_k)), k = that evaluation's
+ * index within its run.  After mm_minimize_to_tol with max_iter = j and
+ * tol = 0 these are tau_{j-1}, T(m_j), U(m_j) and j. */
+int mm_last_step(mm_ctx* ctx, int sample, mm_step_info* info);
+
 /* Per-kernel timing with HIP events on the context's stream.
  * mm_profile(ctx, mask) records an event pair around every launch of each
  * kernel whose bit is set in mask (bit k = kernel id k; 0 stops recording)

@@ -117,20 +117,23 @@ def default_tau0(Ms):
     return 1e-3 / Ms
 
 
-def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb_switch=0.0):
+def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb_switch=0.0,
+             keep_states=False):
     """Relax m0 with the BB midpoint scheme until the torque is below tol.
 
     Returns a dict with the final m, the number of updates ``iters``, the
     number of effective-field evaluations ``heff_evals`` (= iters + 1, the
     unit counted in the paper's Tab. 1), ``converged``, the final torque and
     energy, and when ``record`` is set the per-iteration tau, torque and
-    energy traces.
+    energy traces; with ``keep_states`` also every iterate m_0, m_1, ... in
+    ``states``.
     """
     Ms = problem.Ms
     tau = default_tau0(Ms) if tau0 is None else float(tau0)
     m = normalise(np.array(m0, dtype=np.float64))
     m_prev = g_prev = None
     taus, torques, energies = [], [], []
+    states = [m.copy()] if keep_states else None
     k = 0
     while True:
         terms = problem.field_terms(m)
@@ -143,7 +146,7 @@ def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb
         if T < tol or k >= max_iter:
             return {"m": m, "iters": k, "heff_evals": k + 1, "converged": T < tol,
                     "torque": T, "energy": float(sum(problem.energy_terms(m, terms))),
-                    "taus": taus, "torques": torques, "energies": energies}
+                    "taus": taus, "torques": torques, "energies": energies, "states": states}
         if k > 0:
             s = m - m_prev
             y = g - g_prev
@@ -155,6 +158,8 @@ def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb
             taus.append(tau)
         m_prev, g_prev = m, g
         m = normalise(midpoint_step(m, H, tau))
+        if keep_states:
+            states.append(m.copy())
         k += 1
 
 

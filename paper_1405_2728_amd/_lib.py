@@ -54,6 +54,7 @@ SIGNATURES = {
     "mm_energy_grads": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(C.c_double)]),
     "mm_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
+    "mm_last_step": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(StepInfo)]),
     "mm_counters": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mm_rows_per_block": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "mm_supported": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),

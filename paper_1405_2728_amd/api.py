@@ -163,6 +163,13 @@ class Context:
         return {"status": rc, "converged": rc == 0, "iters": r.iters,
                 "heff_evals": r.heff_evals, "torque": r.torque, "energy": r.energy}
 
+    def last_step(self, sample):
+        """tau of the most recent update, torque and energy of the most
+        recent evaluation and its index k (mm_last_step)."""
+        si = _lib.StepInfo()
+        self._check(self._lib.mm_last_step(self._h, sample, C.byref(si)))
+        return {"tau": si.tau, "torque": si.torque, "energy": si.energy, "k": si.k}
+
     def hysteresis_sweep(self, ms, H, tol=1e-6, max_iter=100000):
         """ms: list of n_samples magnetisation tensors; H: [n_samples, n_fields, 3]
         (A/m).  Returns (<m> [S, F, 3], iters [S, F], status)."""

@@ -11,11 +11,22 @@ relax(ctx, sample, m0, Ms, A, Ku, H, u, tol, ...)
     solved by conjugate gradients, then dJ/dtheta = -lam . d(dU/dm)/dtheta.
     m* does not depend differentiably on m0 (it is locally constant within
     a basin), so m0 receives no gradient.
+
+Both keep the material and field their forward pass used and set them on
+the context again before the backward pass computes derivatives, so that
+several forward calls on one context and sample (with different
+parameters) before a single backward give each call its own gradients.
+Setting them resets that sample's minimiser state.
 """
 
 import torch
 
 from .api import MMError
+
+
+def _saved(Ms, A, Ku, H, u):
+    """Detached copies of the parameters of one forward call."""
+    return tuple(t.detach().clone() for t in (Ms, A, Ku, H)) + (u,)
 
 
 def _material(ctx, sample, Ms, A, Ku, H, u):
@@ -33,6 +44,7 @@ class _Energy(torch.autograd.Function):
         _material(lib, sample, Ms, A, Ku, H, u)
         E, _ = lib.energy(sample, m)
         fctx.lib, fctx.sample = lib, sample
+        fctx.mat = _saved(Ms, A, Ku, H, u)
         fctx.ku_map = Ku.dim() > 0
         fctx.devs = [t.device for t in (Ms, A, Ku, H)]
         fctx.save_for_backward(m)
@@ -41,6 +53,7 @@ class _Energy(torch.autograd.Function):
     @staticmethod
     def backward(fctx, go):
         (m,) = fctx.saved_tensors
+        _material(fctx.lib, fctx.sample, *fctx.mat)
         g = fctx.lib.energy_grads(fctx.sample, m)
         s = go.to(m.device)
         dKu = g["Ku"] if fctx.ku_map else g["Ku"].sum()
@@ -67,6 +80,7 @@ class _Relax(torch.autograd.Function):
         if not r["converged"]:
             raise MMError(r["status"], "relaxation did not reach the tolerance")
         fctx.lib, fctx.sample = lib, sample
+        fctx.mat = _saved(Ms, A, Ku, H, u)
         fctx.ku_map = Ku.dim() > 0
         fctx.devs = [t.device for t in (Ms, A, Ku, H)]
         fctx.adj = (adj_tol, adj_max_iter)
@@ -77,6 +91,7 @@ class _Relax(torch.autograd.Function):
     def backward(fctx, gm):
         (m,) = fctx.saved_tensors
         lib, sample = fctx.lib, fctx.sample
+        _material(lib, sample, *fctx.mat)
         lam, _, _, rc = lib.adjoint_solve(sample, m, gm.contiguous(), tol=fctx.adj[0],
                                           max_iter=fctx.adj[1])
         if rc != 0:

@@ -1664,6 +1664,20 @@ int mm_counters(mm_ctx* c, int sample, int64_t* heff_evals, int64_t* iters) {
   return MM_OK;
 }
 
+int mm_last_step(mm_ctx* c, int sample, mm_step_info* info) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!info) return fail(c, MM_EINVAL, "null pointer");
+  Sample& s = c->smp[sample];
+  rc = read_state(c, s);
+  if (rc != MM_OK) return rc;
+  info->tau = s.st_host->last_tau;
+  info->torque = s.st_host->torque;
+  info->energy = s.st_host->energy;
+  info->k = s.st_host->last_k;
+  return MM_OK;
+}
+
 int mm_profile(mm_ctx* c, int mask) {
   if (!c || mask < 0) return MM_EINVAL;
   prof_collect(c);

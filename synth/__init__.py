@@ -114,3 +114,20 @@ def batched_platelets(n_samples=64, c=3):
                         fields=loop_fields(40.0, 2.0, h), Ms=8.0e5, A=1.3e-11,
                         Ku=float(ku[s]), u=(1.0, 0.0, 0.0), tol=1e-6))
     return out
+
+
+def sp1_loop(edge="long", cell=10e-9, step_mT=1.0):
+    """Standard Problem 1 stand-in loop (Sec. 4): a 2000 x 1000 x 20 nm
+    permalloy film (Ms 8e5 A/m, A 1.3e-11 J/m, Ku 500 J/m^3 along the long
+    edge x), field along the long edge tilted 1 degree toward y ("long") or
+    along the short edge tilted 1 degree toward x ("short"), +-50 mT loop in
+    step_mT steps, start along the field with 1e-3 noise.  Seeds: 10 (long
+    edge), 11 (short edge), plus 2 for 5 nm cells."""
+    deg = {"long": 1.0, "short": 89.0}[edge]
+    n = (int(round(2e-6 / cell)), int(round(1e-6 / cell)), int(round(20e-9 / cell)))
+    rng = rng_for((10 if edge == "long" else 11) + (2 if cell < 7.5e-9 else 0))
+    h = tilted(deg)
+    m0 = uniform_with_noise(h, *n, 1e-3, rng)
+    return dict(name="SP1 %s edge, %g nm cells, %g mT steps" % (edge, cell * 1e9, step_mT),
+                n=n, d=(cell,) * 3, m0=m0, fields=loop_fields(50.0, step_mT, h), h=h,
+                tol=1e-6, **PERMALLOY)

@@ -7,7 +7,6 @@ single-precision form with its defect correction (a double-precision
 reference pass every poll_every iterations, batched like the iteration);
 "mixed_plain" is the form without it."""
 
-import os
 import sys
 
 import numpy as np
@@ -25,8 +24,7 @@ def torch_cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1405_2728_amd import _build
-    if not os.path.exists(_build.lib_path()):
-        _build.build(verbose=False)
+    _build.ensure_built()
     return torch
 
 

@@ -19,7 +19,6 @@ reference here, validated against the oracle on the same grid (H_eff to
   perturbed run's are or next to a switch, same-basin |dm|_inf within twice
   the perturbed run's)."""
 
-import os
 import sys
 
 import numpy as np
@@ -36,8 +35,7 @@ def torch_cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1405_2728_amd import _build
-    if not os.path.exists(_build.lib_path()):
-        _build.build(verbose=False)
+    _build.ensure_built()
     return torch
 
 

@@ -8,10 +8,12 @@ reference's max-norm):
   scaled by the small tensor entries near the 6-cell switch.
 * mixed (FP32 convolution) effective field 1e-5 (single-precision FFTs of
   length ~1e3 give ~1e-6).
-* iterates: the BB map amplifies rounding; 1e-9 after 10 iterations.
+* iterates (10 steps): near-uniform start 1e-11 on m, 1e-9 on tau; random
+  start (chaotic amplification of rounding) 10x the oracle's own departure
+  from a start perturbed by 1e-15, tau 1e-8.  The benchmarked kernels'
+  iterates are compared in test_gpu_wave_parity.py.
 """
 
-import os
 import sys
 
 import numpy as np
@@ -31,8 +33,7 @@ def torch_cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1405_2728_amd import _build
-    if not os.path.exists(_build.lib_path()):
-        _build.build(verbose=False)
+    _build.ensure_built()
     return torch
 
 
@@ -151,14 +152,14 @@ def test_heff_mixed_precision(torch_cuda, shape):
     ctx.close()
 
 
-@pytest.mark.parametrize("start,tol_m,tol_tau", [
-    # near-uniform start (as in the benchmarked loop): moderate BB steps
-    ("noise", 1e-11, 1e-9),
-    # random start: the first BB steps rotate cells by up to ~pi, so the
-    # ~1e-10 relative rounding of the tiny first s and y is amplified
-    ("random", 1e-7, 1e-6),
-])
-def test_iterates_match_oracle(torch_cuda, start, tol_m, tol_tau):
+@pytest.mark.parametrize("start", ["noise", "random"])
+def test_iterates_match_oracle(torch_cuda, start):
+    """Ten single steps (mm_minimize_step: evaluation kernels of this small
+    grid, stand-alone update) against the oracle's iterates.  Near-uniform
+    start: m within 1e-11, tau 1e-9 relative.  Random start: the first BB
+    steps rotate cells by up to ~pi and amplify rounding chaotically; m is
+    bounded by 10x the departure of the oracle from its own run started at
+    m0 perturbed by 1e-15 (largest of five draws, ~6e-9 here), tau by 1e-8."""
     torch = torch_cuda
     nx, ny, nz = 20, 12, 2
     d = (5e-9,) * 3
@@ -172,7 +173,16 @@ def test_iterates_match_oracle(torch_cuda, start, tol_m, tol_tau):
     ctx, P = make(torch, "fp64", nx, ny, nz, d, H=H)
     m = torch.tensor(m0, device="cuda")
     ref = om.minimize(P, m0, tol=0.0, max_iter=10, record=True)
-    taus, errs = [], []
+    if start == "random":
+        self_dev = 0.0
+        for seed in range(5):
+            p = np.random.default_rng(100 + seed).standard_normal(m0.shape)
+            alt = om.minimize(P, om.normalise(m0 + 1e-15 * p), tol=0.0, max_iter=10)
+            self_dev = max(self_dev, float(np.max(np.abs(alt["m"] - ref["m"]))))
+        tol_m, tol_tau = max(1e-8, 10 * self_dev), 1e-8
+    else:
+        tol_m, tol_tau = 1e-11, 1e-9
+    taus = []
     for k in range(10):
         info = ctx.minimize_step(0, m)
         taus.append(info["tau"])
@@ -180,7 +190,7 @@ def test_iterates_match_oracle(torch_cuda, start, tol_m, tol_tau):
         assert abs(info["torque"] - ref["torques"][k]) < 1e-9 * ref["torques"][k]
     err = np.max(np.abs(m.cpu().numpy() - ref["m"]))
     tau_err = np.max(np.abs(np.array(taus) / np.array(ref["taus"]) - 1))
-    say("  10-iterate max diff", err, "tau rel", tau_err)
+    say("  10-iterate max diff", err, "tau rel", tau_err, "bound", tol_m)
     assert err < tol_m
     assert tau_err < tol_tau
     ctx.close()

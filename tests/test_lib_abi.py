@@ -14,8 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 @pytest.fixture(scope="module")
 def lib():
-    if not os.path.exists(_build.lib_path()):
-        _build.build(verbose=False)
+    _build.ensure_built()
     return _lib.load()
 
 
