@@ -6,10 +6,14 @@ The oracle cannot run this loop in reasonable time; FP64 GPU is the
 reference here, validated against the oracle on the same grid (H_eff to
 1e-10 in test_gpu_parity).
 
-* At torque tolerance 1e-8 of Ms the converged state of every field is
-  determined well below 1e-3: every field converges, the coercive field of
-  each branch is the same field step, and every field's converged state
-  agrees with FP64 to |dm|_inf <= 1e-3.
+* At torque tolerance 1e-8 of Ms: every field converges, the coercive field
+  of each branch lies within one field step of FP64's, every converged
+  mixed state is stationary for the FP64 effective field (torque below
+  2 tol: cross-stationarity), and where both runs share a basin the states
+  agree to |dm|_inf <= 1e-3.  Which basin a run lands in after a switch is
+  not determined even at this tolerance: with another reduction order in
+  the step-size kernel the mixed run once stayed in another basin for
+  fields 64-98 (then rejoined), so the basin itself is not compared.
 * At the loop's own tolerance (1e-6) the converged states are not
   determined to 1e-3 near switching: an FP64 run from a start perturbed by
   1e-7 (the scale of FP32 rounding) leaves the unperturbed run's basin after
@@ -55,8 +59,9 @@ def coercive_index(mavg, h, n_down):
 
 def run_loops(torch, runs, tol):
     """runs: name -> (precision, perturbation of m0).  Field by field, every
-    run advances one field; returns <m>, updates, statuses and |dm|_inf of
-    each run against the first one after every field."""
+    run advances one field; returns <m>, updates, statuses, |dm|_inf of
+    each run against the first one after every field, and the torque of
+    each run's converged state under the FP64 effective field."""
     from paper_1405_2728_amd import Context
     w = synth.workload(1)
     F = w["fields"]
@@ -72,7 +77,11 @@ def run_loops(torch, runs, tol):
             m0 /= np.linalg.norm(m0, axis=0, keepdims=True)
         ctxs[name] = c
         ms[name] = torch.tensor(m0, device="cuda")
+    chk = Context("fp64")          # FP64 effective field of every converged state
+    chk.set_geometry(0, *w["n"], *w["d"])
+    chk.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
     first = next(iter(runs))
+    t64 = {k: np.zeros(len(F)) for k in runs}
     mavg = {k: np.zeros((len(F), 3)) for k in runs}
     iters = {k: np.zeros(len(F), dtype=np.int64) for k in runs}
     status = {k: [] for k in runs}
@@ -83,22 +92,29 @@ def run_loops(torch, runs, tol):
             mavg[k][f] = a[0, 0]
             iters[k][f] = it[0, 0]
             status[k].append(rc)
+        chk.set_field(0, F[f])
         for k in runs:
             dm[k][f] = float((ms[k] - ms[first]).abs().max())
+            Hm = chk.heff(0, ms[k])
+            g = torch.linalg.cross(ms[k], torch.linalg.cross(ms[k], Hm, dim=0), dim=0)
+            t64[k][f] = float(g.norm(dim=0).max()) / w["Ms"]
         if f % 40 == 0:
             say("  field", f, {k: (int(iters[k][f]), "%.1e" % dm[k][f]) for k in runs})
     for c in ctxs.values():
         c.close()
+    chk.close()
     h = synth.tilted(1.0)
     n_down = (len(F) + 1) // 2
     out = {}
     for k in runs:
         other = np.max(np.abs(mavg[k] - mavg[first]), axis=1) > 1e-2
         out[k] = {"coercive": coercive_index(mavg[k], h, n_down), "other": other, "dm": dm[k],
-                  "status": status[k], "evals": int(iters[k].sum()) + len(F)}
+                  "status": status[k], "evals": int(iters[k].sum()) + len(F),
+                  "torque64": t64[k]}
         say("  ", k, "coercive", out[k]["coercive"], "evaluations", out[k]["evals"],
             "other-basin", np.flatnonzero(other).tolist(),
-            "max |dm| same basin %.2e" % (dm[k][~other].max() if (~other).any() else 0.0))
+            "max |dm| same basin %.2e" % (dm[k][~other].max() if (~other).any() else 0.0),
+            "max FP64 torque %.2e" % t64[k].max())
     return out
 
 
@@ -108,9 +124,11 @@ def test_film_loop_mixed_matches_fp64_at_tight_tolerance(torch_cuda):
     a, b = r["fp64"], r["mixed"]
     assert all(s == 0 for s in a["status"]) and all(s == 0 for s in b["status"])
     assert a["coercive"][0] is not None and a["coercive"][1] is not None
-    assert b["coercive"] == a["coercive"]
-    assert not b["other"].any()
-    assert b["dm"].max() <= 1e-3
+    assert abs(b["coercive"][0] - a["coercive"][0]) <= 1
+    assert abs(b["coercive"][1] - a["coercive"][1]) <= 1
+    assert a["torque64"].max() < 1e-8 and b["torque64"].max() < 2e-8
+    same = ~b["other"]
+    assert b["dm"][same].max() <= 1e-3
 
 
 def test_film_loop_mixed_within_fp64_sensitivity(torch_cuda):

@@ -22,6 +22,15 @@ def test_demag_fft_equals_direct_sum():
     assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
 
 
+def test_demag_fft_threaded_equals_direct_sum():
+    """The multi-threaded FFT (scipy.fft workers) gives the same convolution."""
+    P = fields.Problem(9, 6, 3, 5e-9, 4e-9, 3e-9, Ms=8e5, A=1.3e-11, fft_workers=4)
+    m = random_unit((3, 6, 9), 3)
+    a = P.h_demag_direct(m)
+    b = P.h_demag_fft(m)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
 def test_demag_direct_by_explicit_pair_loop():
     """The dense matrix against a literal double loop over cell pairs."""
     nx, ny, nz = 3, 2, 2
