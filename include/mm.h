@@ -138,6 +138,23 @@ int mm_reset(mm_ctx* ctx, int sample);
  * (device in m, device out H, both [3][N] double). */
 int mm_heff(mm_ctx* ctx, int sample, const double* m, double* H);
 
+/* mm_heff without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same effective field as mm_heff, with the
+ * convolution's spectrum held in a fixed array of the library (32 MiB per
+ * GPU, kept until the process ends) instead of the sample's buffers.  The
+ * caller still passes m and H (device [3][N] double).  Requirements: the
+ * device that was current at mm_set_geometry is current (else MM_ESTATE);
+ * the spectrum, 48 (Px/2+1) ny nz bytes in double precision (half that in
+ * MM_MIXED), plus on the full 3-D path 48 (Px/2+1) Py nz bytes, fits the
+ * 32 MiB (else MM_EINVAL with the size in mm_last_error; the 400 x 200 x 4
+ * film needs 17.2 MB).  Calls and host-side code make no hipMalloc, hipFree
+ * or other allocating call.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero: each call writes the spectrum before reading it. */
+int mm_heff_static(mm_ctx* ctx, int sample, const double* m, double* H);
+
 /* Individual field terms at m; each output is a device [3][N] double or
  * NULL to skip it. */
 int mm_field_terms(mm_ctx* ctx, int sample, const double* m, double* H_demag,

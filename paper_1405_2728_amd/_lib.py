@@ -33,6 +33,7 @@ SIGNATURES = {
     "mm_set_field": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
     "mm_reset": (C.c_int, [C.c_void_p, C.c_int]),
     "mm_heff": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "mm_heff_static": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "mm_field_terms": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p]),
     "mm_energy": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double),

@@ -125,6 +125,14 @@ class Context:
         self._check(self._lib.mm_heff(self._h, sample, _dev_ptr(m, n, "m"), _dev_ptr(out, n, "H")))
         return out
 
+    def heff_static(self, sample, m, out):
+        """mm_heff_static: the effective field with the library's fixed
+        scratch array (no allocation by the library; out is the caller's)."""
+        n = self._n3(sample)
+        self._check(self._lib.mm_heff_static(self._h, sample, _dev_ptr(m, n, "m"),
+                                             _dev_ptr(out, n, "H")))
+        return out
+
     def field_terms(self, sample, m):
         n = self._n3(sample)
         hd, hex_, han = (self._new_field(sample) for _ in range(3))

@@ -36,6 +36,7 @@ enum { PATH_NONE = 0, PATH_THIN = 1, PATH_3D = 2 };
 
 struct Sample {
   bool has_geom = false, has_mat = false;
+  int dev = -1;               // device that was current at mm_set_geometry
   int nx = 0, ny = 0, nz = 0, N = 0;
   double dx = 0, dy = 0, dz = 0, V = 0;
   int path = PATH_NONE;
@@ -451,6 +452,8 @@ struct EvalOut {
   bool zeeman = true;         // false: linear part of H_eff only (no H_ext)
   bool unit_A = false;        // exchange with A = 1 (derivative of H_ex by A)
   const int* done = nullptr;  // flag that skips the demag and local passes
+  void* spec = nullptr;       // spectrum buffer in place of the sample's (NULL: its own)
+  void* B = nullptr;          // 3-D path: y-transformed spectrum likewise
 };
 
 LocalArgs local_args(const Sample& s, bool unit_A = false, bool zeeman = true) {
@@ -580,7 +583,9 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   MinState* mst = o.iterate ? s.st : nullptr;
   const int* done = mst ? &mst->done : o.done;
   double* mm = const_cast<double*>(m);
-  const Conv v = conv_main(c, s);
+  Conv v = conv_main(c, s);
+  if (o.spec) v.spec = o.spec;
+  if (o.B) v.B = o.B;
   const bool corr = o.iterate && use_ref(c, s);
   {
     Timer t(c, KID_XF);
@@ -1160,6 +1165,38 @@ int read_scal(mm_ctx* c, Sample& s, int n) {
 
 }  // namespace
 
+// ---- allocation-free evaluation ----------------------------------------------
+// mm_heff_static keeps the spectrum of its convolution (and, on the 3-D path,
+// the y-transformed spectrum) in this array instead of the sample's own
+// buffers.  Every GPU the library runs on holds one copy until the process
+// ends; host code reaches it only through the per-device address taken with
+// hipGetSymbolAddress (the array's name is a host-side stand-in).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), resolved once per device.
+int scratch_address(mm_ctx* c, int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, MM_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(c, MM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return MM_OK;
+}
+
+}  // namespace
+
 // ============================================================================
 extern "C" {
 
@@ -1225,6 +1262,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.dx = dx; s.dy = dy; s.dz = dz;
   s.V = dx * dy * dz;
   s.path = path;
+  if (hipGetDevice(&s.dev) != hipSuccess) s.dev = -1;
   s.Px = pad_x(nx, mr);
   s.M = s.Px / 2;
   const bool full = path == PATH_3D;
@@ -1374,6 +1412,36 @@ int mm_heff(mm_ctx* c, int sample, const double* m, double* H) {
   EvalOut o;
   o.H = H;
   enqueue_eval(c, c->smp[sample], m, o);
+  HIPCHK(c, hipGetLastError());
+  return MM_OK;
+}
+
+int mm_heff_static(mm_ctx* c, int sample, const double* m, double* H) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !H) return fail(c, MM_EINVAL, "null buffer");
+  Sample& s = c->smp[sample];
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev != s.dev)
+    return fail(c, MM_ESTATE, "mm_heff_static: call with the device of mm_set_geometry current");
+  const size_t creal = single(c) ? sizeof(float) : sizeof(double);
+  const size_t spec = (size_t)(s.M + 1) * 3 * s.nz * s.ny * 2 * creal;
+  const size_t spec_al = (spec + 255) / 256 * 256;
+  const size_t nB = s.path == PATH_3D ? (size_t)(s.M + 1) * s.Py * 3 * s.nz * 2 * creal : 0;
+  const size_t need = spec_al + nB;
+  if (need > kStaticScratchBytes)
+    return fail(c, MM_EINVAL, "mm_heff_static: this grid needs " + std::to_string(need) +
+                                  " bytes of scratch, more than its maximum of " +
+                                  std::to_string(kStaticScratchBytes));
+  unsigned char* base = nullptr;
+  rc = scratch_address(c, dev, &base);
+  if (rc != MM_OK) return rc;
+  EvalOut o;
+  o.H = H;
+  o.spec = base;
+  o.B = nB ? base + spec_al : nullptr;
+  enqueue_eval(c, s, m, o);
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
