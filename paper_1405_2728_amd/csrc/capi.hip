@@ -752,7 +752,7 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
         const bool match = x ? (d[i].M == g.a && d[i].R == g.b)
                              : (d[i].Py == g.a && d[i].nz == g.b && d[i].tstride == g.t);
         if (!match) continue;
-        const int nb = x ? d[i].nb3 : d[i].M;   // yz: block 0 carries kx = 0 and M
+        const int nb = x ? d[i].nb3 : d[i].M + 1;   // yz: one block per column kx = 0..M
         for (int blk = 0; blk < nb; ++blk) v.push_back({i, blk});
       }
       xcd_order(v);

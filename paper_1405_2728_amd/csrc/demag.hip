@@ -15,8 +15,8 @@
 //           kx = M: both columns are spectra of real data, packed as
 //           re + i*im and separated by Hermitian symmetry in ky.
 //   inv_x   A[kx][z][y][c] -> half-length inverse -> H_d rows (double)
-//   yz_wave as yz_thin, with register-resident wave FFTs (one wave per z
-//           layer, Py = 64..512) and one block per column kx = 0..M
+//   yz_wave as yz_thin, with register wave FFTs (one wave per layer and
+//           component, Py = 64..512) and one block per column kx = 0..M
 // The factor -Ms/(M Py) of the inverse transforms is applied in yz_thin.
 #include "mm_device.h"
 #include "mm_kernels.h"
@@ -252,34 +252,22 @@ k_yz_thin(cx<T>* __restrict__ A, int ny, int Py, int M, const T* __restrict__ Tt
 }
 
 // ---------------------------------------------------------------------------
-// y-FFT, tensor product with z convolution, inverse y-FFT; wave FFT version.
-// Block = NZ wavefronts, wave z owns layer z (three components); block kx
-// handles column kx in 1..M-1, and block 0 the two real-input columns kx = 0
-// and kx = M packed as re + i im (so that M blocks, not M + 1, fill the
-// machine).  Lane g holds the frequencies ky = wfft_freq(g, d), d < 8.  The
-// tensor slab of the column is copied to LDS with direct global-to-LDS loads
-// while the forward transforms run; the z convolution exchanges two slots d
-// at a time through LDS.
-// Block 0: with U = F0 + i FM the transform of the packed column (F0, FM the
-// Hermitian spectra of the two real columns), P = (U(k) + conj U(-k))/2 = F0
-// and Q = (U(k) - conj U(-k))/2 = i FM, and T0 P + TM Q = H0 + i HM is the
-// transform of the packed result.  Frequency -k lies in slot 7 - d of lane
-// g' (k1 = g/8, c = g%8: g' = 8 (VL - k1) + 7 - c for k1 >= 1, g' = 8 - c
-// for k1 = 0), except on lane 0, whose slots pair as (d, 8 - d).  In
-// registers, slots 0..3 are turned into P(k) and slots 4..7 into Q(-q) (one
-// shuffle per slot pair); pass 1 applies T0 to slots 0..3, the kx = M tensor
-// then replaces T0 in LDS and pass 2 applies it to slots 4..7 (at -q); a
-// second shuffle forms V(k) = V1(k) + V2(k) with V1(-k) = conj V1(k) and
-// V2(-k) = -conj V2(k).  Frequencies 0 and n/2 (lane 0, slots 0 and 4) see a
-// real diagonal tensor: real part with T0, imaginary part with TM.
-// LDS: [tensor slab, padded to 1 KiB] [transposes | exchange buffer] [4 diagonal
-// tensor entries per layer for block 0].
+// y-FFT, tensor product with the z convolution, inverse y-FFT; wave FFT
+// version.  One block per column kx = 0..M; 3 NZ wavefronts, wave w = 3 z + c
+// transforms component c of layer z (64 VL points, zero padded beyond ny)
+// with the register wave FFT, using its own LDS slice for the transposes and
+// then to hold its 8 output slots (slot d of lane g: frequency
+// wfft_freq(g, d)).  After a barrier the product runs per position: wave d
+// (d < 8) takes slot d of every lane, reads the 3 NZ spectra of that
+// position, forms every output layer and component (symmetric 3x3 tensor,
+// direct convolution over the layers) and writes them back in place; after a
+// second barrier each wave transforms its slice back and stores the ny kept
+// rows.  The tensor slab of the column is copied to LDS by direct
+// global-to-LDS loads while the forward transforms run.  Columns 0 and M are
+// spectra of real rows: their results are real (the imaginary part, rounding
+// only, is dropped).
+// LDS: [3 NZ slices of yz_slice<VL>() elements][tensor slab, 1 KiB multiple].
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src) {
-  return mk(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
-}
-
 // h += T f for one tensor entry set t = (xx, yy, zz, xy, xz, yz) of the
 // mixed (kx, ky, dz) domain: xz and yz are coefficients of i; sy, sz are the
 // parity signs of ky < 0 and dz < 0.
@@ -294,234 +282,161 @@ __device__ __forceinline__ void tensor_term(const T* __restrict__ t, T sy, T sz,
   h[2] = add(h[2], add(add(scl(ifx, xz), scl(ify, yz)), scl(f[2], zz)));
 }
 
-// Offset (complex elements) of block 0's diagonal tensor entries after the
-// transposes and the exchange buffer; they take 3 NZ elements (6 NZ reals),
-// followed by lane 0's saved values (24 per layer).
-template <int VL, int NZ, bool HALF>
-__host__ __device__ constexpr int yz_pt_offset() {
-  return NZ * wfft_buf<VL, HALF>() > NZ * 3 * 2 * 64 ? NZ * wfft_buf<VL, HALF>() : NZ * 3 * 2 * 64;
+// complex elements of one wave's slice: the transposes of the wave FFT
+// (72 VL) and the 8 slots of 64 lanes
+template <int VL>
+__host__ __device__ constexpr int yz_slice() { return VL * 72 > 512 ? VL * 72 : 512; }
+
+// bytes of LDS of one yz block
+template <typename T, int VL, int NZ>
+__host__ __device__ constexpr size_t yz_lds_bytes(int tstride) {
+  return (size_t)3 * NZ * yz_slice<VL>() * sizeof(cx<T>) +
+         ((size_t)tstride * sizeof(T) + 1023) / 1024 * 1024;
 }
 
-template <typename T, int VL, int NZ, bool HALF>
+// Every output layer of one position: dst[(zo 3 + c) SL] = scale
+// sum_zp T(zo - zp) f[zp], tensor rows at tl + (|dz| nk + kyp) 6 in LDS.
+// PAIRS: two output layers per round (more independent chains; double
+// precision), else one.
+template <typename T, int NZ, bool PAIRS>
+__device__ __forceinline__ void yz_position(const T* tl, int nk, int kyp, T sy, T scale,
+                                            const cx<T> (&f)[NZ][3], cx<T>* dst, int SL) {
+  if constexpr (PAIRS && NZ > 1) {
+#pragma unroll 1
+    for (int z0 = 0; z0 < NZ; z0 += 2) {
+      const int z1 = z0 + 1 < NZ ? z0 + 1 : z0;
+      cx<T> h0[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+      cx<T> h1[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+#pragma unroll
+      for (int zp = 0; zp < NZ; ++zp) {
+        const int da = z0 - zp, db = z1 - zp;
+        tensor_term<T>(tl + ((da < 0 ? -da : da) * nk + kyp) * 6, sy, da < 0 ? T(-1) : T(1),
+                       f[zp], h0);
+        tensor_term<T>(tl + ((db < 0 ? -db : db) * nk + kyp) * 6, sy, db < 0 ? T(-1) : T(1),
+                       f[zp], h1);
+      }
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        dst[(z0 * 3 + cc) * SL] = scl(h0[cc], scale);
+        if (z1 != z0) dst[(z1 * 3 + cc) * SL] = scl(h1[cc], scale);
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int zo = 0; zo < NZ; ++zo) {
+      cx<T> h[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+#pragma unroll
+      for (int zp = 0; zp < NZ; ++zp) {
+        const int dz = zo - zp;
+        tensor_term<T>(tl + ((dz < 0 ? -dz : dz) * nk + kyp) * 6, sy, dz < 0 ? T(-1) : T(1),
+                       f[zp], h);
+      }
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) dst[(zo * 3 + cc) * SL] = scl(h[cc], scale);
+    }
+  }
+}
+
+template <typename T, int VL, int NZ>
 __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int M,
                                              const T* __restrict__ Tt, int tstride, T scale,
                                              const cx<T>* __restrict__ twy,
                                              const int* __restrict__ done, int kx) {
-  // the stop flag is read while the first column loads are in flight
-  const int dn = done != nullptr ? *done : 0;
   constexpr int n = 64 * VL;
-  constexpr int NG = 8 * VL;
-  constexpr int DC = 2;                       // slots exchanged per round
+  constexpr int NG = 8 * VL;                 // lanes holding output slots
+  constexpr int NW = 3 * NZ;
   constexpr int nk = n / 2 + 1;
+  constexpr int SL = yz_slice<VL>();
   extern __shared__ __align__(16) unsigned char smem[];
-  const int tl_bytes = ((tstride * (int)sizeof(T) + 1023) / 1024) * 1024;
-  T* tl = reinterpret_cast<T*>(smem);
-  cx<T>* sm = reinterpret_cast<cx<T>*>(smem + tl_bytes);
+  cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
+  T* tl = reinterpret_cast<T*>(smem + (size_t)NW * SL * sizeof(cx<T>));
   const int lane = threadIdx.x & 63;
-  const int z = threadIdx.x >> 6;
-  cx<T>* tbuf = sm + z * wfft_buf<VL, HALF>();   // wave-private transpose buffer
-  cx<T>* xbuf = sm;                              // exchange buffer [z][c][DC][64]
-  const size_t slab = (size_t)3 * NZ * ny;
-  const bool pair = kx == 0;                     // columns 0 and M, packed
-  cx<T>* Ak = A + (size_t)kx * slab;
-  cx<T>* AM = A + (size_t)M * slab;
-  auto load = [&](int c, int y) -> cx<T> {
-    if (y >= ny) return mk(T(0), T(0));
-    const size_t e = ((size_t)z * ny + y) * 3 + c;
-    return pair ? mk(Ak[e].x, AM[e].x) : Ak[e];
-  };
-  // column loads (three components of layer z), one component ahead
-  cx<T> F[3][8];
-  cx<T> xin[2][VL];
+  const int w = threadIdx.x >> 6;
+  const int z = w / 3, c = w - 3 * (w / 3);
+  cx<T>* slice = sm + w * SL;
+  cx<T>* Ak = A + (size_t)kx * 3 * NZ * ny;
+  cx<T> v[VL];
 #pragma unroll
-  for (int r = 0; r < VL; ++r) xin[0][r] = load(0, lane + 64 * r);
-  if (dn != 0) return;             // before any LDS copy is started
-  // tensor slab -> LDS, 16 bytes per lane, no registers involved
-  auto stage_tensor = [&](const T* slab_src) {
+  for (int r = 0; r < VL; ++r) {
+    const int y = lane + 64 * r;
+    v[r] = y < ny ? Ak[((size_t)z * ny + y) * 3 + c] : mk(T(0), T(0));
+  }
+  // the stop flag is read while the column loads are in flight
+  if (done != nullptr && *done != 0) return;
+  {
+    // tensor slab -> LDS, 16 bytes per lane, no registers involved
     const int nchunk = tstride * (int)sizeof(T) / 16;
-    const unsigned char* src = reinterpret_cast<const unsigned char*>(slab_src);
-    for (int base = z * 64; base < nchunk; base += NZ * 64) {
+    const unsigned char* src = reinterpret_cast<const unsigned char*>(Tt + (size_t)kx * tstride);
+    for (int base = w * 64; base < nchunk; base += NW * 64) {
       const int ch = min(base + lane, nchunk - 1);
       __builtin_amdgcn_global_load_lds(
           (const void*)(src + (size_t)ch * 16),
-          (__attribute__((address_space(3))) void*)(smem + (size_t)base * 16), 16, 0, 0);
-    }
-  };
-  stage_tensor(Tt + (size_t)kx * tstride);
-  // block 0: diagonal entries T0(dz, n/2) and TM(dz, 0), [2][NZ][3]
-  constexpr int pt_off = yz_pt_offset<VL, NZ, HALF>();
-  T* pt = reinterpret_cast<T*>(sm + pt_off);
-  if (pair && threadIdx.x < 6 * NZ) {
-    const int t = threadIdx.x, which = t / (3 * NZ), dz = (t % (3 * NZ)) / 3, c = t % 3;
-    pt[t] = Tt[(size_t)(which ? M : 0) * tstride + (dz * nk + (which ? 0 : n / 2)) * 6 + c];
-  }
-  // forward transforms
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (c < 2) {
-#pragma unroll
-      for (int r = 0; r < VL; ++r) xin[(c + 1) & 1][r] = load(c + 1, lane + 64 * r);
-    }
-    wfft_forward<T, VL, HALF>(xin[c & 1], F[c], tbuf, twy, lane);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  __builtin_amdgcn_s_waitcnt(0);   // tensor copy complete (this wave's part)
-  __syncthreads();                 // ... and every wave's; transposes done
-  // block 0: lane 0 pairs its own slots (d, 8 - d); its values are kept in
-  // LDS [z][c][8] around the two register transforms
-  const int k1 = lane >> 3, cl = lane & 7;
-  const int gp = lane >= NG ? lane : (k1 >= 1 ? 8 * (VL - k1) + 7 - cl : 8 - cl);
-  cx<T>* l0 = sm + pt_off + 3 * NZ + z * 24;
-  auto keep_lane0 = [&]() {
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 8; ++d) l0[c * 8 + d] = F[c][d];
-    }
-    __builtin_amdgcn_wave_barrier();
-  };
-  if (pair) {
-    // slots 0..3 -> P(k), slots 4..7 -> Q(-q)
-    keep_lane0();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const cx<T> uj = F[c][j], u7 = F[c][7 - j];
-        const cx<T> pa = shfl_cx(u7, gp), pb = shfl_cx(uj, gp);
-        cx<T> wj = scl(add(uj, conj(pa)), T(0.5));
-        cx<T> w7 = scl(sub(pb, conj(u7)), T(0.5));
-        if (lane == 0) {
-          wj = j == 0 ? uj : scl(add(uj, conj(l0[c * 8 + ((8 - j) & 7)])), T(0.5));
-          w7 = j <= 2 ? scl(sub(l0[c * 8 + j + 1], conj(u7)), T(0.5)) : u7;
-        }
-        F[c][j] = wj;
-        F[c][7 - j] = w7;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+          (__attribute__((address_space(3))) void*)((unsigned char*)tl + (size_t)base * 16), 16,
+          0, 0);
     }
   }
-  // Tensor product.  Block 0: slots 0..3 with the kx = 0 tensor, slots 4..7
-  // (at -q) with the kx = M tensor staged in between; lane 0's slots 0 and 4
-  // (ky = 0, n/2) see real diagonal tensors, real part T0, imaginary part TM.
-  const T* p0 = pt;              // T0(dz, n/2) diagonal
-  const T* pM = pt + 3 * NZ;     // TM(dz, 0) diagonal
-  constexpr int DCP = NZ == 1 ? 1 : DC;   // one layer: no exchange needed
+  cx<T> u[8];
+  wfft_forward<T, VL, false>(v, u, slice, twy, lane);
+  __builtin_amdgcn_wave_barrier();
+  if (lane < NG) {
 #pragma unroll
-  for (int d0 = 0; d0 < 8; d0 += DCP) {
-    if (pair && d0 == 4) {
-      // every wave has finished with T0 (barrier at the end of the round)
-      stage_tensor(Tt + (size_t)M * tstride);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
-    if constexpr (NZ > 1) {
-      if (lane < NG) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int dl = 0; dl < DCP; ++dl) xbuf[((z * 3 + c) * DCP + dl) * 64 + lane] = F[c][d0 + dl];
-      }
-      __syncthreads();
-    }
+    for (int d = 0; d < 8; ++d) slice[d * 64 + lane] = u[d];
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's tensor copies have landed
+  __syncthreads();                 // ... and every wave's, and every slice is written
+  for (int d = w; d < 8; d += NW) {
     if (lane < NG) {
+      const int q = wfft_freq<VL>(lane, d);
+      const bool neg = q > n / 2;
+      cx<T> f[NZ][3];
 #pragma unroll
-      for (int dl = 0; dl < DCP; ++dl) {
-        const int d = d0 + dl;
-        const int q = wfft_freq<VL>(lane, d);
-        const bool neg = q > n / 2;
-        const bool at_minus = pair && d >= 4;
-        const int kyp = (neg || at_minus) ? n - q : q;
-        const T sy = (neg && !at_minus) ? T(-1) : T(1);
-        const bool diag = pair && lane == 0 && (d == 0 || d == 4);
-        cx<T> h[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
-#pragma unroll 1
-        for (int zp = 0; zp < NZ; ++zp) {
-          const int dz = z - zp;
-          const int dzp = dz < 0 ? -dz : dz;
-          const T sz = dz < 0 ? T(-1) : T(1);
-          cx<T> f[3];
-          if constexpr (NZ > 1) {
+      for (int zp = 0; zp < NZ; ++zp)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f[c] = xbuf[((zp * 3 + c) * DCP + dl) * 64 + lane];
-          } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) f[c] = F[c][d];
-          }
-          if (!diag) {
-            tensor_term<T>(tl + (dzp * nk + kyp) * 6, sy, sz, f, h);
-          } else {
-            const T* tre = d == 0 ? tl + (dzp * nk) * 6 : p0 + dzp * 3;
-            const T* tim = d == 0 ? pM + dzp * 3 : tl + (dzp * nk + n / 2) * 6;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) h[c] = add(h[c], mk(tre[c] * f[c].x, tim[c] * f[c].y));
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) F[c][d] = scl(h[c], scale);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    if constexpr (NZ > 1) __syncthreads();
-  }
-  if (pair) {
-    // V(k) = V1(k) + V2(k) on slots 0..3, conj V1(-q) - conj V2(-q) on 4..7
-    keep_lane0();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const cx<T> vj = F[c][j], v7 = F[c][7 - j];
-        const cx<T> a = shfl_cx(v7, gp), b = shfl_cx(vj, gp);
-        cx<T> rj = add(vj, a);
-        cx<T> r7 = sub(conj(b), conj(v7));
-        if (lane == 0) {
-          rj = j == 0 ? vj : add(vj, l0[c * 8 + ((8 - j) & 7)]);
-          r7 = j <= 2 ? sub(conj(l0[c * 8 + j + 1]), conj(v7)) : v7;
-        }
-        F[c][j] = rj;
-        F[c][7 - j] = r7;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+        for (int cc = 0; cc < 3; ++cc) f[zp][cc] = sm[(zp * 3 + cc) * SL + d * 64 + lane];
+      yz_position<T, NZ, sizeof(T) == 8>(tl, nk, neg ? n - q : q, neg ? T(-1) : T(1), scale, f,
+                                         sm + d * 64 + lane, SL);
     }
   }
-  // inverse transforms and store of the ny kept rows (block 0: unpacked)
+  __syncthreads();
+  if (lane < NG) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    cx<T> xo[VL];
-    wfft_inverse<T, VL, HALF>(F[c], xo, tbuf, twy, lane);
+    for (int d = 0; d < 8; ++d) u[d] = slice[d * 64 + lane];
+  }
+  __builtin_amdgcn_wave_barrier();
+  // the inverse reads the twiddles again: an offset the compiler cannot see
+  // to be zero (ny < 2^30) keeps it from holding the forward pass's twiddles
+  // in registers across the product
+  const int zoff = ny >> 30;
+  cx<T> xo[VL];
+  wfft_inverse<T, VL, false>(u, xo, slice, twy + zoff, lane);
+  const bool real_col = kx == 0 || kx == M;
 #pragma unroll
-    for (int r = 0; r < VL; ++r) {
-      const int y = lane + 64 * r;
-      if (y >= ny) continue;
-      const size_t e = ((size_t)z * ny + y) * 3 + c;
-      if (pair) {
-        Ak[e] = mk(xo[r].x, T(0));
-        AM[e] = mk(xo[r].y, T(0));
-      } else {
-        Ak[e] = xo[r];
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
+  for (int r = 0; r < VL; ++r) {
+    const int y = lane + 64 * r;
+    if (y < ny) Ak[((size_t)z * ny + y) * 3 + c] = real_col ? mk(xo[r].x, T(0)) : xo[r];
   }
 }
 
-template <typename T, int VL, int NZ, bool HALF>
-__global__ void __launch_bounds__(64 * NZ, 2)
+// waves per SIMD the yz kernels are compiled for: double precision holds
+// one 4-layer block per CU (LDS), single precision two
+template <typename T>
+__host__ __device__ constexpr int yz_waves_per_eu() { return sizeof(T) == 8 ? 3 : 6; }
+
+template <typename T, int VL, int NZ>
+__global__ void __launch_bounds__(192 * NZ, yz_waves_per_eu<T>())
 k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int tstride, T scale,
           const cx<T>* __restrict__ twy, const int* __restrict__ done) {
-  yz_wave_body<T, VL, NZ, HALF>(A, ny, M, Tt, tstride, scale, twy, done, blockIdx.x);
+  yz_wave_body<T, VL, NZ>(A, ny, M, Tt, tstride, scale, twy, done, blockIdx.x);
 }
 
-// Batched: items[b] = (sample, kx), kx < M; all samples share Py and nz.
-template <typename T, int VL, int NZ, bool HALF>
-__global__ void __launch_bounds__(64 * NZ, 2)
+// Batched: items[b] = (sample, kx), kx <= M; all samples share Py and nz.
+template <typename T, int VL, int NZ>
+__global__ void __launch_bounds__(192 * NZ, yz_waves_per_eu<T>())
 k_yz_wave_b(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   const WorkItem it = items[blockIdx.x];
   const BatchDesc& d = descs[it.sample];
-  yz_wave_body<T, VL, NZ, HALF>((cx<T>*)d.spec, d.ny, d.M, (const T*)d.Tt, d.tstride, (T)d.scale,
-                                (const cx<T>*)d.twy, &d.st->done, it.block);
+  yz_wave_body<T, VL, NZ>((cx<T>*)d.spec, d.ny, d.M, (const T*)d.Tt, d.tstride, (T)d.scale,
+                          (const cx<T>*)d.twy, &d.st->done, it.block);
 }
 
 // ---------------------------------------------------------------------------
@@ -641,14 +556,10 @@ static void yz_dispatch(hipStream_t s, void* A, int ny, int Py, int M, const T* 
 template <typename T, int VL, int NZ>
 static void yz_wave_dispatch(hipStream_t s, void* A, int ny, int M, const T* Tt, int tstride,
                              T scale, const void* twy, const int* done) {
-  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;     // keep two blocks per CU in FP64
-  // transposes | exchange buffer, then block 0's diagonal tensor entries
-  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ + 24 * NZ;
-  const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
-  const size_t lds = tl + un * sizeof(cx<T>);
-  auto k = k_yz_wave<T, VL, NZ, HALF>;
+  const size_t lds = yz_lds_bytes<T, VL, NZ>(tstride);
+  auto k = k_yz_wave<T, VL, NZ>;
   set_lds(k, lds);
-  hipLaunchKernelGGL(k, dim3(M), dim3(64 * NZ), lds, s, (cx<T>*)A, ny, M, Tt, tstride, scale,
+  hipLaunchKernelGGL(k, dim3(M + 1), dim3(192 * NZ), lds, s, (cx<T>*)A, ny, M, Tt, tstride, scale,
                      (const cx<T>*)twy, done);
 }
 
@@ -693,13 +604,10 @@ void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const
 template <typename T, int VL, int NZ>
 static void yzb_dispatch(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
                          int tstride) {
-  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
-  const size_t un = (size_t)yz_pt_offset<VL, NZ, HALF>() + 3 * NZ + 24 * NZ;
-  const size_t tl = ((tstride * sizeof(T) + 1023) / 1024) * 1024;
-  const size_t lds = tl + un * sizeof(cx<T>);
-  auto k = k_yz_wave_b<T, VL, NZ, HALF>;
+  const size_t lds = yz_lds_bytes<T, VL, NZ>(tstride);
+  auto k = k_yz_wave_b<T, VL, NZ>;
   set_lds(k, lds);
-  hipLaunchKernelGGL(k, dim3(n_items), dim3(64 * NZ), lds, s, descs, items);
+  hipLaunchKernelGGL(k, dim3(n_items), dim3(192 * NZ), lds, s, descs, items);
 }
 
 template <typename T, int VL>
