@@ -51,7 +51,7 @@ WORKLOADS = {
     "cube": (2, 3, "cube 128^3 cells of 2 nm, full 3-D demag, BB midpoint minimiser, "
                    "random start, 60 mT at 2 deg from z", [256, 256, 256]),
 }
-EXTRA_WORKLOADS = ("batched", "adjoint", "loop")
+EXTRA_WORKLOADS = ("batched", "adjoint", "loop", "cube-sweep")
 
 
 def parse():
@@ -272,6 +272,67 @@ def host_cores():
     return max(1, n)
 
 
+def cube_sweep(torch, fields_idx=None, max_iter=100000, oracle_check=True):
+    """The 128^3 cube (2 nm cells, random start) relaxed at H = 0, then at
+    20, 40, ..., 200 mT along z + 2 degrees, in FP64 and in the mixed form
+    side by side, field by field.  Per field: <m> of both, iterations, the
+    mixed state's distance to the FP64 state (|dm|_inf), the torque of the
+    mixed state under the FP64 effective field (cross-stationarity), and the
+    first field at which every cell points along the field (m.h > 0) in
+    each form.  With oracle_check, the oracle's torque at the first and
+    last FP64 states (its own FFT convolution at 256^3)."""
+    import synth
+    from paper_1405_2728_amd import Context
+    w = synth.workload(2)
+    F = w["fields"] if fields_idx is None else w["fields"][list(fields_idx)]
+    h = F[-1] / np.linalg.norm(F[-1])
+    ctx, m = {}, {}
+    for prec in ("fp64", "mixed"):
+        c = Context(prec)
+        c.set_geometry(0, *w["n"], *w["d"])
+        c.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
+        ctx[prec], m[prec] = c, torch.tensor(w["m0"], device="cuda")
+    rows, states = [], []
+    for f, H in enumerate(F):
+        r = {"field_mT": float(np.linalg.norm(H) / synth.MT)}
+        for prec in ("fp64", "mixed"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a, it, rc = ctx[prec].hysteresis_sweep([m[prec]], H[None, None], tol=w["tol"],
+                                                   max_iter=max_iter)
+            torch.cuda.synchronize()
+            mh = (m[prec] * torch.tensor(h, device="cuda")[:, None, None, None]).sum(0)
+            r[prec] = {"mavg": [float(v) for v in a[0, 0]], "iters": int(it[0, 0]),
+                       "status": int(rc), "seconds": time.perf_counter() - t0,
+                       "all_along_field": bool((mh > 0).all())}
+        ctx["fp64"].set_field(0, H)
+        Hm = ctx["fp64"].heff(0, m["mixed"])
+        g = torch.linalg.cross(m["mixed"], torch.linalg.cross(m["mixed"], Hm, dim=0), dim=0)
+        r["mixed_torque_fp64_field"] = float(g.norm(dim=0).max()) / w["Ms"]
+        r["dm_inf"] = float((m["mixed"] - m["fp64"]).abs().max())
+        rows.append(r)
+        print("cube field %d %s" % (f, json.dumps(r)), file=sys.stderr, flush=True)
+        if oracle_check and f in (0, len(F) - 1):
+            states.append((H.copy(), m["fp64"].cpu().numpy()))
+    for c in ctx.values():
+        c.close()
+    out = {"fields": rows}
+    for prec in ("fp64", "mixed"):
+        out["first_saturated_index_" + prec] = next(
+            (i for i, r in enumerate(rows) if r[prec]["all_along_field"]), None)
+    out["max_dm_inf"] = max(r["dm_inf"] for r in rows)
+    out["max_mixed_torque_fp64_field"] = max(r["mixed_torque_fp64_field"] for r in rows)
+    if oracle_check:
+        from oracle import fields as of, minimizer as om
+        P = of.Problem(*w["n"], *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"],
+                       fft_workers=host_cores())
+        out["oracle_torque_at_fp64_states"] = []
+        for H, mg in states:
+            P.H_ext = H
+            out["oracle_torque_at_fp64_states"].append(om.torque(mg, P.heff(mg), P.Ms))
+    return out
+
+
 def cpu_baseline(w, iters, field, label, workers=1):
     """The oracle (as it stands) on `iters` minimiser iterations of the same
     workload; its FFT convolution on `workers` threads (scipy.fft), the rest
@@ -323,6 +384,12 @@ def main():
         print(json.dumps({"metric": "H_eff evaluations and seconds per hysteresis loop "
                                     "(201 fields)", "n_gpus": 1, "data": "synthetic",
                           "bb_switch": a.bb_switch, "loops": r}))
+        return
+    if a.workload == "cube-sweep":
+        r = cube_sweep(torch)
+        r.update({"metric": "128^3 cube sweep 0..200 mT, FP64 vs mixed per field",
+                  "n_gpus": 1, "data": "synthetic"})
+        print(json.dumps(r))
         return
     if a.workload == "adjoint":
         r = run_adjoint(torch)

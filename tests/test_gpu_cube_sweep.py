@@ -1,0 +1,80 @@
+"""Precision stress case: the 128^3 cube of 2 nm cells (Ms 1e6 A/m, A 1.5e-11
+J/m, Ku 5e4 J/m^3 along z, random start), relaxed at H = 0 and then at 20, 40
+and 60 mT along z + 2 degrees, in FP64 and in the mixed form (FP32
+convolution with its defect correction) side by side (full 3-D demag path,
+paper Sec. 2 stop rule, tol 1e-6).
+
+Per field: both forms converge; the mixed state is stationary for the FP64
+effective field (torque < 2 tol: cross-stationarity) and lies within 1e-3 of
+the FP64 state (|dm|_inf: the two land in the same basin over these fields;
+measured <= 1e-4); the oracle's own torque at the FP64 states of the first
+and last field is below tol (its FFT convolution at 256^3).  Beyond 60 mT a
+switching event sends the two forms into mirror-image metastable states (the
+energy is symmetric under y -> -y with the field in the x-z plane); bench.py
+--workload cube-sweep reports the whole 0..200 mT sweep.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fields as of, minimizer as om
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1405_2728_amd import _build
+    _build.ensure_built()
+    return torch
+
+
+def test_cube_sweep_mixed_against_fp64(torch_cuda):
+    torch = torch_cuda
+    from paper_1405_2728_amd import Context
+    w = synth.workload(2)
+    F = w["fields"][:4]
+    ctx, m = {}, {}
+    for prec in ("fp64", "mixed"):
+        c = Context(prec)
+        c.set_geometry(0, *w["n"], *w["d"])
+        c.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
+        ctx[prec], m[prec] = c, torch.tensor(w["m0"], device="cuda")
+    keep = {}
+    for f, H in enumerate(F):
+        out = {}
+        for prec in ("fp64", "mixed"):
+            a, it, rc = ctx[prec].hysteresis_sweep([m[prec]], H[None, None], tol=w["tol"])
+            assert rc == 0, (prec, f, rc)
+            out[prec] = (a[0, 0], int(it[0, 0]))
+        ctx["fp64"].set_field(0, H)
+        Hm = ctx["fp64"].heff(0, m["mixed"])
+        g = torch.linalg.cross(m["mixed"], torch.linalg.cross(m["mixed"], Hm, dim=0), dim=0)
+        T = float(g.norm(dim=0).max()) / w["Ms"]
+        dm = float((m["mixed"] - m["fp64"]).abs().max())
+        say("  field %d: iters fp64 %d mixed %d, |dm|_inf %.2e, mixed torque (FP64 field) %.2e"
+            % (f, out["fp64"][1], out["mixed"][1], dm, T))
+        assert T < 2 * w["tol"]
+        assert dm < 1e-3
+        assert np.max(np.abs(out["fp64"][0] - out["mixed"][0])) < 1e-4
+        if f in (0, len(F) - 1):
+            keep[f] = (H.copy(), m["fp64"].cpu().numpy())
+    for c in ctx.values():
+        c.close()
+    P = of.Problem(*w["n"], *w["d"], Ms=w["Ms"], A=w["A"], Ku=w["Ku"], u=w["u"], fft_workers=8)
+    for f, (H, mg) in keep.items():
+        P.H_ext = H
+        T = om.torque(mg, P.heff(mg), P.Ms)
+        say("  oracle torque at the FP64 state of field %d: %.3e" % (f, T))
+        assert T < w["tol"] * 1.01
