@@ -375,8 +375,13 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
           0, 0);
     }
   }
+  // Both transforms read their twiddles through an offset the compiler
+  // cannot see to be zero (kx, ny < 2^30): it then reloads them for the
+  // inverse instead of holding the forward pass's in registers across the
+  // product, and does not hoist them above the column loads.
+  const int zoff = (kx >> 30) + (ny >> 30);
   cx<T> u[8];
-  wfft_forward<T, VL, false>(v, u, slice, twy, lane);
+  wfft_forward<T, VL, false>(v, u, slice, twy + (kx >> 30), lane);
   __builtin_amdgcn_wave_barrier();
   if (lane < NG) {
 #pragma unroll
@@ -384,18 +389,22 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
   }
   __builtin_amdgcn_s_waitcnt(0);   // this wave's tensor copies have landed
   __syncthreads();                 // ... and every wave's, and every slice is written
-  for (int d = w; d < 8; d += NW) {
-    if (lane < NG) {
-      const int q = wfft_freq<VL>(lane, d);
-      const bool neg = q > n / 2;
-      cx<T> f[NZ][3];
+  // wave w forms slot w (and, with fewer than 8 waves, slots w + NW, ...)
+  auto product = [&](int d) {
+    const int q = wfft_freq<VL>(lane, d);
+    const bool neg = q > n / 2;
+    cx<T> f[NZ][3];
 #pragma unroll
-      for (int zp = 0; zp < NZ; ++zp)
+    for (int zp = 0; zp < NZ; ++zp)
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) f[zp][cc] = sm[(zp * 3 + cc) * SL + d * 64 + lane];
-      yz_position<T, NZ, sizeof(T) == 8>(tl, nk, neg ? n - q : q, neg ? T(-1) : T(1), scale, f,
-                                         sm + d * 64 + lane, SL);
-    }
+      for (int cc = 0; cc < 3; ++cc) f[zp][cc] = sm[(zp * 3 + cc) * SL + d * 64 + lane];
+    yz_position<T, NZ, sizeof(T) == 8>(tl, nk, neg ? n - q : q, neg ? T(-1) : T(1), scale, f,
+                                       sm + d * 64 + lane, SL);
+  };
+  if (w < 8 && lane < NG) product(w);
+  if constexpr (NW < 8) {
+    for (int d = w + NW; d < 8; d += NW)
+      if (lane < NG) product(d);
   }
   __syncthreads();
   if (lane < NG) {
@@ -403,10 +412,6 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
     for (int d = 0; d < 8; ++d) u[d] = slice[d * 64 + lane];
   }
   __builtin_amdgcn_wave_barrier();
-  // the inverse reads the twiddles again: an offset the compiler cannot see
-  // to be zero (ny < 2^30) keeps it from holding the forward pass's twiddles
-  // in registers across the product
-  const int zoff = ny >> 30;
   cx<T> xo[VL];
   wfft_inverse<T, VL, false>(u, xo, slice, twy + zoff, lane);
   const bool real_col = kx == 0 || kx == M;
