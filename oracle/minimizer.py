@@ -43,9 +43,24 @@ R10 Step switch (optional, bb_switch = kappa > 0).  Sec. 2 contrasts its
     tau1, each formed with |s.y| and guarded as in R5.  Since
     (s.y)^2 <= (s.s)(y.y), tau2 <= tau1: kappa > 1 always takes tau2, a
     tiny kappa always tau1.  Parity unpinned against Exl et al.'s own rule.
+R11 Non-monotone line search (optional safeguard of the step choice; the
+    paper uses none).  Along the curve tau -> m(tau) of eq. (7) the energy
+    falls at rate dU/dtau = -mu0 Ms V sum_i |g_i|^2 at tau = 0 (first order
+    m(tau) = m - tau g, and dU/dm_i = -mu0 Ms V H_eff,i).  A trial step tau
+    is accepted when U(m(tau)) <= C - rho tau mu0 Ms V sum |g|^2, with the
+    reference value C the Zhang-Hager weighted average of the accepted
+    energies (C_0 = U_0, Q_0 = 1; after an accepted step
+    Q' = eta Q + 1, C' = (eta Q C + U_new) / Q'); otherwise tau is
+    multiplied by sigma and the trial repeated from the same m (at most
+    ls_max times, after which the last trial is taken).  Every trial is an
+    effective-field evaluation; the BB quotients use the accepted s and y,
+    and a rejected candidate's "previous tau" is the accepted one.
+    Defaults eta = 0.85, rho = 1e-4, sigma = 0.5, ls_max = 30.
 """
 
 import numpy as np
+
+MU0 = 4e-7 * np.pi
 
 
 def cross(a, b):
@@ -163,11 +178,75 @@ def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb
         k += 1
 
 
-def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0.0):
+def minimize_ls(problem, m0, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0.0,
+                eta=0.85, rho=1e-4, sigma=0.5, ls_max=30, record=False, keep_states=False):
+    """The minimiser with the non-monotone line search of reading R11.
+
+    Same return dict as minimize (``iters`` = accepted updates,
+    ``heff_evals`` = evaluations including rejected trials), plus
+    ``backtracks`` (rejected trials) and, with ``record``, the accepted
+    taus, torques, energies and the reference values C per accepted state.
+    """
+    Ms, V = problem.Ms, problem.V
+    c = MU0 * Ms * V
+
+    def evaluate(m):
+        terms = problem.field_terms(m)
+        H = terms["demag"] + terms["exchange"] + terms["anisotropy"] + terms["zeeman"]
+        g = projected_direction(m, H)
+        gg = np.sum(g * g, axis=0)
+        return (H, g, float(np.sqrt(np.max(gg))) / Ms, float(np.sum(gg)),
+                float(sum(problem.energy_terms(m, terms))))
+
+    tau = default_tau0(Ms) if tau0 is None else float(tau0)
+    m = normalise(np.array(m0, dtype=np.float64))
+    H, g, T, G, E = evaluate(m)
+    evals, k, back = 1, 0, 0
+    C, Q = E, 1.0
+    taus, torques, energies, refs = [], [T], [E], [C]
+    states = [m.copy()] if keep_states else None
+    while True:
+        if T < tol or k >= max_iter:
+            return {"m": m, "iters": k, "heff_evals": evals, "converged": T < tol, "torque": T,
+                    "energy": E, "backtracks": back, "taus": taus, "torques": torques,
+                    "energies": energies, "refs": refs, "states": states}
+        nb = 0
+        while True:
+            mt = normalise(midpoint_step(m, H, tau))
+            Ht, gt, Tt, Gt, Et = evaluate(mt)
+            evals += 1
+            if Et <= C - rho * tau * c * G or nb >= ls_max:
+                break
+            tau *= sigma
+            nb += 1
+            back += 1
+        s, y = mt - m, gt - g
+        m, H, g, T, G, E = mt, Ht, gt, Tt, Gt, Et
+        Qn = eta * Q + 1.0
+        C = (eta * Q * C + E) / Qn
+        Q = Qn
+        k += 1
+        if record:
+            taus.append(tau)
+            torques.append(T)
+            energies.append(E)
+            refs.append(C)
+        if keep_states:
+            states.append(m.copy())
+        cand = bb_candidate(k, float(np.sum(s * s)), float(np.sum(s * y)), float(np.sum(y * y)),
+                            bb_switch)
+        if cand is not None:
+            tau = cand
+
+
+def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0.0,
+          line_search=False):
     """Warm-started hysteresis sweep (Sec. 4, reading R9).
 
     ``fields`` is [n_fields, 3] in A/m.  For each field the minimiser runs
-    once from the previous field's result.  Returns per-field mean
+    once from the previous field's result (with ``line_search`` the
+    safeguarded form of reading R11, its reference value restarting at every
+    field).  Returns per-field mean
     magnetisation <m> [n_fields, 3], iteration counts, energies and the final
     magnetisation.
     """
@@ -175,17 +254,20 @@ def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0
     fields = np.asarray(fields, dtype=np.float64).reshape(-1, 3)
     mavg = np.zeros((len(fields), 3))
     iters = np.zeros(len(fields), dtype=np.int64)
+    evals = np.zeros(len(fields), dtype=np.int64)
     energy = np.zeros(len(fields))
     conv = np.zeros(len(fields), dtype=bool)
     states = []
     for f, H in enumerate(fields):
         problem.H_ext = H.copy()
-        res = minimize(problem, m, tol=tol, max_iter=max_iter, tau0=tau0, bb_switch=bb_switch)
+        run = minimize_ls if line_search else minimize
+        res = run(problem, m, tol=tol, max_iter=max_iter, tau0=tau0, bb_switch=bb_switch)
         m = res["m"]
         mavg[f] = m.reshape(3, -1).mean(axis=1)
         iters[f] = res["iters"]
+        evals[f] = res["heff_evals"]
         energy[f] = res["energy"]
         conv[f] = res["converged"]
         states.append(m.copy())
-    return {"m": m, "mavg": mavg, "iters": iters, "energy": energy,
+    return {"m": m, "mavg": mavg, "iters": iters, "heff_evals": evals, "energy": energy,
             "converged": conv, "states": states}

@@ -314,3 +314,77 @@ def test_relaxation_lowers_energy_c0_like():
     assert r["converged"]
     assert r["energy"] < P.energy(m0)
     assert r["torques"][-1] < 1e-6
+
+
+# ------------------------------------------------- non-monotone line search (R11)
+def test_energy_slope_along_the_midpoint_curve():
+    """dU/dtau at tau = 0 along tau -> m(tau) of eq. (7) is -mu0 Ms V sum |g|^2
+    (the slope the line search's sufficient-decrease test uses), checked by a
+    central difference of the energy."""
+    P = small_problem()
+    m = random_unit((2, 4, 6), 31)
+    H = P.heff(m)
+    g = mz.projected_direction(m, H)
+    slope = -MU0 * P.Ms * P.V * float(np.sum(g * g))
+    h = 1e-9 / P.Ms
+    up = P.energy(mz.normalise(mz.midpoint_step(m, H, h)))
+    dn = P.energy(mz.normalise(mz.midpoint_step(m, H, -h)))
+    fd = (up - dn) / (2 * h)
+    assert abs(fd - slope) < 1e-6 * abs(slope)
+
+
+def test_line_search_accepts_plain_bb_steps_on_a_benign_case():
+    """Near-uniform start in a strong field: every BB step already decreases
+    the reference value enough, nothing is rejected and the iterates are the
+    plain alternation's, bit for bit."""
+    P = small_problem(H_ext=(8e4, 0.0, 0.0))
+    m0 = mz.normalise(np.stack([np.ones((2, 4, 6)), 0.01 * np.ones((2, 4, 6)),
+                                0.005 * np.ones((2, 4, 6))]))
+    a = mz.minimize(P, m0, tol=1e-8, keep_states=True)
+    b = mz.minimize_ls(P, m0, tol=1e-8, keep_states=True)
+    assert b["backtracks"] == 0
+    assert b["iters"] == a["iters"] and b["heff_evals"] == a["heff_evals"]
+    for x, y in zip(a["states"], b["states"]):
+        assert np.array_equal(x, y)
+
+
+def test_line_search_rejects_an_energy_rise():
+    """A first step far too long (tau0 = 1e-3 / Ms * 3e3) raises the energy in
+    the plain method; the line search rejects it, shrinks tau until the
+    sufficient-decrease test holds, and every accepted energy respects its
+    reference value (checked with the recorded C and an independent slope)."""
+    P = small_problem()
+    m0 = random_unit((2, 4, 6), 32)
+    tau0 = 3.0 / P.Ms
+    E0 = P.energy(m0)
+    plain = mz.minimize(P, m0, tol=0.0, max_iter=1, tau0=tau0)
+    assert plain["energy"] > E0                      # the plain first step climbs
+    r = mz.minimize_ls(P, m0, tol=1e-6, tau0=tau0, record=True, keep_states=True)
+    assert r["converged"] and r["backtracks"] >= 1
+    assert r["energies"][1] < E0
+    c = MU0 * P.Ms * P.V
+    for k in range(1, len(r["energies"])):
+        m = r["states"][k - 1]
+        g = mz.projected_direction(m, P.heff(m))
+        bound = r["refs"][k - 1] - 1e-4 * r["taus"][k - 1] * c * float(np.sum(g * g))
+        assert r["energies"][k] <= bound * (1 + 1e-14) + 1e-30
+    assert max(r["energies"]) <= r["energies"][0]
+
+
+def test_line_search_reaches_a_stationary_minimum():
+    """From a random start the safeguarded iteration converges to a state the
+    plain torque test accepts, with no more evaluations than the plain
+    alternation here, and to the same energy on the 4-cell problem that a
+    general optimiser solves."""
+    P = small_problem()
+    m0 = random_unit((2, 4, 6), 33)
+    r = mz.minimize_ls(P, m0, tol=1e-8)
+    assert r["converged"]
+    assert mz.torque(r["m"], P.heff(r["m"]), P.Ms) < 1e-8
+    q = fields.Problem(2, 2, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=2e4, u=(1, 0, 0),
+                       H_ext=(1e4, 8e3, 0.0))
+    m1 = random_unit((1, 2, 2), 34)
+    a = mz.minimize(q, m1, tol=1e-10)
+    b = mz.minimize_ls(q, m1, tol=1e-10)
+    assert a["converged"] and b["converged"]
+    assert abs(a["energy"] - b["energy"]) < 1e-9 * abs(a["energy"])
