@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--bb-switch", type=float, default=0.0, metavar="KAPPA",
                    help="with --workload loop: step choice (0 alternation of eq. (12); "
                         "kappa > 0 the ratio switch tau2 if tau2 < kappa tau1)")
+    p.add_argument("--line-search", action="store_true",
+                   help="with --workload loop: the non-monotone line search on every step")
     p.add_argument("--quick", action="store_true",
                    help="only the timed run (for profilers): no profiled pass, no other "
                         "precision, no CPU baseline")
@@ -196,13 +198,15 @@ def run_adjoint(torch):
             "dJ_dA": g["A"], "dJ_dMs": g["Ms"], "status": [int(rc), int(rc2)]}
 
 
-def run_loop(torch, prec, n, d, m0, fields, tol=1e-6, bb_switch=0.0):
+def run_loop(torch, prec, n, d, m0, fields, tol=1e-6, bb_switch=0.0, line_search=False):
     """One device-driven sweep over the whole loop; (evaluations, seconds,
-    <m> per field, status).  bb_switch: the library's step-choice option."""
+    <m> per field, status).  bb_switch, line_search: the library's
+    step-choice options."""
     import synth
     from paper_1405_2728_amd import Context
     ctx = Context(prec)
     ctx.set_option("bb_switch", bb_switch)
+    ctx.set_option("line_search", 1 if line_search else 0)
     ctx.set_geometry(0, *n, *d)
     ctx.set_material(0, synth.PERMALLOY["Ms"], synth.PERMALLOY["A"], synth.PERMALLOY["Ku"],
                      synth.PERMALLOY["u"])
@@ -212,8 +216,9 @@ def run_loop(torch, prec, n, d, m0, fields, tol=1e-6, bb_switch=0.0):
     mavg, iters, rc = ctx.hysteresis_sweep([m], fields[None], tol=tol)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    evals, _ = ctx.counters(0)          # every evaluation, rejected trials included
     ctx.close()
-    return int(iters.sum()) + len(fields), dt, mavg[0], int(rc)
+    return int(evals), dt, mavg[0], int(rc)
 
 
 def coercive_fields_mT(mavg, fields, h):
@@ -227,14 +232,14 @@ def coercive_fields_mT(mavg, fields, h):
     return [None if v is None else float(v) for v in (down, up)]
 
 
-def loops(torch, bb_switch=0.0):
+def loops(torch, bb_switch=0.0, line_search=False):
     import synth
     out = {}
     w = synth.workload(1)
     h = synth.tilted(1.0)
     for prec in ("fp64", "mixed"):
         ev, dt, mavg, rc = run_loop(torch, prec, w["n"], w["d"], w["m0"], w["fields"],
-                                    bb_switch=bb_switch)
+                                    bb_switch=bb_switch, line_search=line_search)
         out["film400x200x4_" + prec] = {"evals_per_loop": ev, "seconds": dt, "evals_per_s": ev / dt,
                                         "coercive_mT": coercive_fields_mT(mavg, w["fields"], h),
                                         "status": rc}
@@ -245,17 +250,17 @@ def loops(torch, bb_switch=0.0):
     # short edge at 5 nm cells (400 x 200 x 4; the long edge at 5 nm is the film
     # above).  Paper Tab. 1 counts for 10 nm, 1 mT: 64814 and 81454 evaluations
     # per loop on other hardware and code (context only).
-    rng = synth.rng_for(10)
-    cases = [("sp1_10nm_long_edge", (200, 100, 2), 10e-9, 1.0, 1.0),
-             ("sp1_10nm_short_edge", (200, 100, 2), 10e-9, 89.0, 1.0),
-             ("sp1_10nm_long_edge_0.5mT", (200, 100, 2), 10e-9, 1.0, 0.5),
-             ("sp1_10nm_short_edge_0.5mT", (200, 100, 2), 10e-9, 89.0, 0.5),
-             ("sp1_5nm_short_edge", (400, 200, 4), 5e-9, 89.0, 1.0)]
-    for name, n, dd, deg, step in cases:
-        hh = synth.tilted(deg)
-        m0 = synth.uniform_with_noise(hh, *n, 1e-3, rng)
-        f = synth.loop_fields(50.0, step, hh)
-        ev, dt, mavg, rc = run_loop(torch, "fp64", n, (dd,) * 3, m0, f, bb_switch=bb_switch)
+    cases = [("sp1_10nm_long_edge", "long", 10e-9, 1.0),
+             ("sp1_10nm_short_edge", "short", 10e-9, 1.0),
+             ("sp1_10nm_long_edge_0.5mT", "long", 10e-9, 0.5),
+             ("sp1_10nm_short_edge_0.5mT", "short", 10e-9, 0.5),
+             ("sp1_5nm_short_edge", "short", 5e-9, 1.0)]
+    for name, edge, cell, step in cases:
+        w = synth.sp1_loop(edge, cell, step)
+        f = w["fields"]
+        ev, dt, mavg, rc = run_loop(torch, "fp64", w["n"], w["d"], w["m0"], f,
+                                    bb_switch=bb_switch, line_search=line_search)
+        hh = w["h"]
         out[name] = {"fields": len(f), "evals_per_loop": ev, "evals_per_field": ev / len(f),
                      "seconds": dt, "coercive_mT": coercive_fields_mT(mavg, f, hh), "status": rc}
         print(name, out[name], file=sys.stderr, flush=True)
@@ -380,10 +385,11 @@ def main():
                           "speedup": (ib / tb) / (iseq / tseq), "status": [rcb, rcs]}))
         return
     if a.workload == "loop":
-        r = loops(torch, a.bb_switch)
+        r = loops(torch, a.bb_switch, a.line_search)
         print(json.dumps({"metric": "H_eff evaluations and seconds per hysteresis loop "
                                     "(201 fields)", "n_gpus": 1, "data": "synthetic",
-                          "bb_switch": a.bb_switch, "loops": r}))
+                          "bb_switch": a.bb_switch, "line_search": a.line_search,
+                          "loops": r}))
         return
     if a.workload == "cube-sweep":
         r = cube_sweep(torch)

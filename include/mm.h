@@ -251,6 +251,21 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * takes tau2 = |s.y|/y.y where tau2 < kappa tau1, else tau1 = s.s/|s.y|,
  * a ratio switch between the two steps in the spirit of the more elaborate
  * switching Sec. 2 attributes to Exl et al.; must be finite and >= 0),
+ * "line_search" (0 or 1, default 0, taken at each reset of the minimiser
+ * state: a non-monotone safeguard of the step, which Sec. 2 does not use.
+ * Every step is a trial m(tau) of eq. (7) from the accepted state, accepted
+ * when U(m(tau)) <= C - ls_rho tau mu0 Ms V sum_i |g_i|^2 (the energy's
+ * slope along eq. (7) at tau = 0 is -mu0 Ms V sum |g|^2) with C the
+ * Zhang-Hager average of the accepted energies (C = U_0 at the start of a
+ * run or field; after an accepted step Q' = ls_eta Q + 1,
+ * C' = (ls_eta Q C + U) / Q'); a rejected trial is repeated from the same
+ * state with tau multiplied by ls_sigma, at most ls_max times.  The stop
+ * rule and the step choice of eq. (12) apply to accepted states; every
+ * trial is one effective-field evaluation (mm_counters counts them).
+ * mm_minimize_step returns MM_EINVAL while it is on; batched sweeps run
+ * per sample), "ls_eta" (in [0, 1], default 0.85), "ls_rho" (in (0, 1),
+ * default 1e-4), "ls_sigma" (in (0, 1), default 0.5), "ls_max" (integer
+ * 0..1000, default 30),
  * "use_graph" (1, with a
  * non-null stream: mm_minimize_to_tol and mm_hysteresis_sweep replay each
  * batch of poll_every iterations after the first as one captured HIP graph;

@@ -84,11 +84,14 @@ struct Sample {
   double* mref = nullptr;
   double* hdref = nullptr;
   long long ref_age = 0;      // iterations since the last reference pass
+  // line search: saved base state and the trial's gradient (on first use)
+  double* ls_mbase = nullptr;
+  double* ls_g2 = nullptr;
   // captured batch of poll_every minimiser iterations (use_graph), valid for
   // the m buffer, batch length, correction flag and material it was made with
   hipGraphExec_t it_graph = nullptr;
   const double* it_graph_m = nullptr;
-  int it_graph_n = 0, it_graph_ref = 0, it_graph_mat = -1;
+  int it_graph_n = 0, it_graph_ref = 0, it_graph_mat = -1, it_graph_ls = 0;
   int mat_version = 0;
   int64_t evals_total = 0, iters_total = 0;
 };
@@ -111,6 +114,7 @@ struct mm_ctx {
   int poll_every = 32;
   long long stall_iters = 500;
   double bb_switch = 0.0;       // step choice: 0 alternation of eq. (12); kappa > 0 ratio switch
+  LineSearch ls = {0, 0.85, 1e-4, 0.5, 30};   // non-monotone line search (off by default)
   int use_graph = 0;
   int batched = 1;              // sweeps of several samples share launches
   int path_pref = 0;            // 0 automatic, 1 thin-film, 2 full 3-D
@@ -194,6 +198,8 @@ void dfree(P*& p) {
 }
 
 void free_sample(Sample& s) {
+  dfree(s.ls_mbase);
+  dfree(s.ls_g2);
   dfree(s.ku_map);
   dfree(s.Tt);
   dfree(s.spec);
@@ -461,6 +467,7 @@ LocalArgs local_args(const Sample& s, bool unit_A = false, bool zeeman = true) {
   a.m = nullptr;
   a.Hd = nullptr;
   a.g = nullptr;
+  a.g_out = nullptr;
   a.s = nullptr;
   a.Hout = nullptr;
   a.Hex_out = nullptr;
@@ -600,6 +607,7 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   LocalArgs a = local_args(s, o.unit_A, o.zeeman);
   a.m = m;
   a.g = o.iterate ? s.g : nullptr;
+  a.g_out = o.iterate && c->ls.on ? s.ls_g2 : nullptr;   // line search: g keeps the base's
   a.s = o.iterate ? s.s : nullptr;
   a.Hout = o.H;
   a.Hex_out = o.Hex;
@@ -660,7 +668,7 @@ struct BatchPlan {
 };
 
 bool batchable(const mm_ctx* c, const Sample& s) {
-  return s.path == PATH_THIN && s.M % 64 == 0 && s.M >= 64 && s.M <= 512 &&
+  return !c->ls.on && s.path == PATH_THIN && s.M % 64 == 0 && s.M >= 64 && s.M <= 512 &&
          yz_wave_ok(s.nz, s.Py) && (!single(c) || !c->refine || s.has_ref);
 }
 
@@ -1043,7 +1051,7 @@ int read_state(mm_ctx* c, Sample& s) {
 int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
   const int ref = use_ref(c, s) ? 1 : 0;
   if (s.it_graph && s.it_graph_m == m && s.it_graph_n == c->poll_every && s.it_graph_ref == ref &&
-      s.it_graph_mat == s.mat_version)
+      s.it_graph_mat == s.mat_version && s.it_graph_ls == c->ls.on)
     return MM_OK;
   if (s.it_graph) (void)hipGraphExecDestroy(s.it_graph);
   s.it_graph = nullptr;
@@ -1064,12 +1072,35 @@ int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
   s.it_graph_n = c->poll_every;
   s.it_graph_ref = ref;
   s.it_graph_mat = s.mat_version;
+  s.it_graph_ls = c->ls.on;
   return MM_OK;
 }
 
+// Line-search buffers of a sample (saved base m and the trial gradient),
+// allocated on the first run with the line search on.
+int ensure_ls(mm_ctx* c, Sample& s) {
+  if (!c->ls.on || s.ls_g2 != nullptr) return MM_OK;
+  if (hipMalloc((void**)&s.ls_mbase, 3ull * s.N * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&s.ls_g2, 3ull * s.N * sizeof(double)) != hipSuccess) {
+    dfree(s.ls_mbase);
+    dfree(s.ls_g2);
+    (void)hipGetLastError();
+    return fail(c, MM_ENOMEM, "device allocation for the line search failed");
+  }
+  return MM_OK;
+}
+
+// Minimiser state reset of a run: BB state, stop rule, step choice and
+// (when on) the line search with the sample's buffers.
+void reset_run(mm_ctx* c, hipStream_t st, Sample& s, double tol, long long max_iter) {
+  launch_reset_state(st, s.st, tau0_of(c, s), tol, max_iter, stall_of(c, s), 0, s.H, c->bb_switch,
+                     c->ls.on ? &c->ls : nullptr, s.ls_mbase, s.ls_g2);
+}
+
 int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
-  launch_reset_state(c->stream, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                     stall_of(c, s), 0, s.H, c->bb_switch);
+  int lrc = ensure_ls(c, s);
+  if (lrc != MM_OK) return lrc;
+  reset_run(c, c->stream, s, tol, (long long)max_iter);
   s.ref_age = kRefStale;
   // full batches after the first replay a captured graph (use_graph on a
   // non-null stream, kernels not being timed); the first batch runs eagerly
@@ -1484,6 +1515,8 @@ int mm_minimize_step(mm_ctx* c, int sample, double* m, mm_step_info* info) {
   int rc = check_sample(c, sample, true);
   if (rc != MM_OK) return rc;
   if (!m) return fail(c, MM_EINVAL, "null buffer");
+  if (c->ls.on)
+    return fail(c, MM_EINVAL, "the line search runs in mm_minimize_to_tol and sweeps only");
   Sample& s = c->smp[sample];
   launch_set_mode(c->stream, s.st, 1);
   enqueue_iteration(c, s, m);
@@ -1575,8 +1608,12 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
   for (int k = 0; k < S; ++k) {
     Sample& s = c->smp[k];
     for (int q = 0; q < 3; ++q) s.H[q] = H[((size_t)k * n_fields) * 3 + q];
-    launch_reset_state(st, s.st, tau0_of(c, s), tol, (long long)max_iter,
-                       stall_of(c, s), 0, s.H, c->bb_switch);
+    const int lrc = ensure_ls(c, s);
+    if (lrc != MM_OK) {
+      cleanup();
+      return lrc;
+    }
+    reset_run(c, st, s, tol, (long long)max_iter);
     launch_sweep_start(st, s.st, fields + (size_t)k * n_fields * 3, n_fields,
                        mavg + (size_t)k * n_fields * 3, its + (size_t)k * n_fields, 1.0 / s.N);
     s.ref_age = kRefStale;
@@ -1688,6 +1725,22 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     if (!(value >= 0.0) || !std::isfinite(value))
       return fail(c, MM_EINVAL, "bb_switch must be finite and >= 0");
     c->bb_switch = value;
+  } else if (!std::strcmp(key, "line_search")) {
+    if (value != 0.0 && value != 1.0) return fail(c, MM_EINVAL, "line_search is 0 or 1");
+    c->ls.on = value != 0.0;
+  } else if (!std::strcmp(key, "ls_eta")) {
+    if (!(value >= 0.0 && value <= 1.0)) return fail(c, MM_EINVAL, "ls_eta must be in [0, 1]");
+    c->ls.eta = value;
+  } else if (!std::strcmp(key, "ls_rho")) {
+    if (!(value > 0.0 && value < 1.0)) return fail(c, MM_EINVAL, "ls_rho must be in (0, 1)");
+    c->ls.rho = value;
+  } else if (!std::strcmp(key, "ls_sigma")) {
+    if (!(value > 0.0 && value < 1.0)) return fail(c, MM_EINVAL, "ls_sigma must be in (0, 1)");
+    c->ls.sigma = value;
+  } else if (!std::strcmp(key, "ls_max")) {
+    if (value < 0 || value > 1000 || value != std::floor(value))
+      return fail(c, MM_EINVAL, "ls_max must be an integer in 0..1000");
+    c->ls.max_back = (int)value;
   } else if (!std::strcmp(key, "stall_iters")) {
     if (value < 0) return fail(c, MM_EINVAL, "stall_iters must be >= 0");
     c->stall_iters = (long long)value;

@@ -30,12 +30,17 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
      const MinState* __restrict__ st, int nx, int ny, int nz, int Px, int R,
      cx<T>* __restrict__ out, const cx<T>* __restrict__ twx, const double* __restrict__ msub,
      double* __restrict__ mcopy) {
-  bool upd = false;
+  bool upd = false, ls_upd = false, retry = false;
   double tau = 0.0;
+  double *mbase = nullptr, *g2 = nullptr;
   if (st != nullptr) {
     if (st->done != 0) return;
     upd = st->pending != 0 && mcopy == nullptr;
     tau = st->last_tau;
+    ls_upd = upd && st->ls.on != 0;
+    retry = st->ls_retry != 0;
+    mbase = st->ls_mbase;
+    g2 = st->ls_g2;
   }
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
@@ -65,6 +70,19 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
           double gi[3], mo[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) gi[c] = g[(size_t)c * N + i];
+          if (ls_upd) {
+            // line search: see the wave-FFT pass below
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              if (retry) {
+                mi[c] = mbase[(size_t)c * N + i];
+              } else {
+                gi[c] = g2[(size_t)c * N + i];
+                mbase[(size_t)c * N + i] = mi[c];
+                const_cast<double*>(g)[(size_t)c * N + i] = gi[c];
+              }
+            }
+          }
           cayley_step(mi, gi, tau, mo);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -146,7 +164,8 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
   }
   __syncthreads();
   fft_lds<1, VPT>(buf, M, q3, M, twx, Px, tid, nthr);
-  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
+  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr &&
+                  (a.st->k > 0 || a.st->ls_trial != 0);
   double part[kNPartial] = {};
   for (int idx = tid; idx < R * nx; idx += nthr) {
     const int r = idx / nx, x = idx - r * nx;
@@ -206,14 +225,23 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
   // The state is read while the first cells' loads are in flight: nothing
   // branches on it before they are issued, and a finished run (done) writes
   // nothing and leaves after phase 1 (the flag is the same for the block).
-  int done = 0, pend = 0;
+  int done = 0, pend = 0, ls = 0, retry = 0;
   double tau = 0.0;
+  double *mbase = nullptr, *g2 = nullptr;
   if (st != nullptr) {
     done = st->done;
     pend = st->pending;
     tau = st->last_tau;
+    ls = st->ls.on;
+    retry = st->ls_retry;
+    mbase = st->ls_mbase;
+    g2 = st->ls_g2;
   }
   const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
+  // line search: the trial starts from the saved base (retry) or from the
+  // accepted state in m with the gradient of its evaluation in g2, which
+  // then become the saved base (mbase, g)
+  const bool ls_upd = upd && ls != 0;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
   T* smr = reinterpret_cast<T*>(smem);
@@ -247,6 +275,18 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
         if (idx >= total) continue;
         const int r = idx / nx, x = idx - r * nx;
         const size_t i = row0 + idx;
+        if (ls_upd) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (retry) {
+              mi[u][c] = mbase[(size_t)c * N + i];
+            } else {
+              gi[u][c] = g2[(size_t)c * N + i];
+              mbase[(size_t)c * N + i] = mi[u][c];
+              const_cast<double*>(g)[(size_t)c * N + i] = gi[u][c];
+            }
+          }
+        }
         if (upd) {
           double mo[3];
           cayley_step(mi[u], gi[u], tau, mo);
@@ -349,6 +389,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   // after phase 1 (LDS writes only)
   const int done = a.done != nullptr ? *a.done : 0;
   const long long kst = a.st != nullptr ? a.st->k : 0;
+  const int lst = a.st != nullptr ? a.st->ls_trial : 0;
   if (a.Hdyn != nullptr)
     for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
   extern __shared__ __align__(16) unsigned char smem[];
@@ -416,7 +457,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   }
   __syncthreads();
   // phase 3: local terms of the rows
-  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && kst > 0;
+  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && (kst > 0 || lst != 0);
   double part[kNPartial] = {};
   {
     constexpr int U = 1;                       // cells per thread per round
@@ -488,6 +529,7 @@ k_xil_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items
   a.m = d.m;
   a.Hd = nullptr;
   a.g = d.g;
+  a.g_out = nullptr;
   a.s = d.s;
   a.Hout = nullptr;
   a.Hex_out = nullptr;

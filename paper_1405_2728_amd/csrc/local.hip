@@ -25,7 +25,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
     for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
   const int N = a.nx * a.ny * a.nz;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr && a.st->k > 0;
+  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr &&
+                  (a.st->k > 0 || a.st->ls_trial != 0);
   double part[kNPartial] = {};
   if (i < N) {
     double hd[3];
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(256) k_mean_finish(const double* __restrict__ 
 
 __global__ void k_reset_state(MinState* st, double tau0, double tol, long long max_iter,
                               long long stall_iters, int mode, double hx, double hy, double hz,
-                              double bb_switch) {
+                              double bb_switch, LineSearch ls, double* ls_mbase, double* ls_g2) {
   MinState z;
   z.tau = tau0;
   z.torque = 0.0;
@@ -197,6 +198,13 @@ __global__ void k_reset_state(MinState* st, double tau0, double tol, long long m
   z.worst = 1;
   z.inv_N = 0.0;
   z.bb_switch = bb_switch;
+  z.ls = ls;
+  z.ls_trial = 0;
+  z.ls_retry = 0;
+  z.ls_nb = 0;
+  z.ls_C = z.ls_Q = z.ls_G = 0.0;
+  z.ls_mbase = ls_mbase;
+  z.ls_g2 = ls_g2;
   *st = z;
 }
 
@@ -222,9 +230,15 @@ __global__ void k_set_mode(MinState* st, int mode) {
 }
 
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
-                        long long stall_iters, int mode, const double H[3], double bb_switch) {
+                        long long stall_iters, int mode, const double H[3], double bb_switch,
+                        const LineSearch* ls, double* ls_mbase, double* ls_g2) {
+  LineSearch off;
+  off.on = 0;
+  off.eta = off.rho = off.sigma = 0.0;
+  off.max_back = 0;
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(1), 0, s, st, tau0, tol, max_iter, stall_iters,
-                     mode, H[0], H[1], H[2], bb_switch);
+                     mode, H[0], H[1], H[2], bb_switch, ls != nullptr ? *ls : off, ls_mbase,
+                     ls_g2);
 }
 
 void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,

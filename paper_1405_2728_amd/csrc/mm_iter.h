@@ -51,8 +51,9 @@ __device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, C
 }
 
 // Local terms of one cell i given its demag field hd: H_eff, g = m x (m x H)
-// (written back when a.g is set) and the eight partial sums
-// [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext, max |g|^2].
+// (written to a.g_out, or back to a.g, when a.g is set) and the partial sums
+// [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext, max |g|^2, sum m,
+// sum |g|^2].
 __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const double hd[3],
                                              bool bb, const CellIn& d, double part[kNPartial]) {
   const int N = a.nx * a.ny * a.nz;
@@ -91,7 +92,9 @@ __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const do
   const double g0 = mi[1] * az - mi[2] * ay;
   const double g1 = mi[2] * ax - mi[0] * az;
   const double g2 = mi[0] * ay - mi[1] * ax;
-  part[7] = fmax(part[7], g0 * g0 + g1 * g1 + g2 * g2);
+  const double gg = g0 * g0 + g1 * g1 + g2 * g2;
+  part[7] = fmax(part[7], gg);
+  part[11] += gg;
   if (a.g != nullptr) {
     if (bb) {
       const double y0 = g0 - d.g[0], y1 = g1 - d.g[1], y2 = g2 - d.g[2];
@@ -99,9 +102,10 @@ __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const do
       part[1] += d.s[0] * y0 + d.s[1] * y1 + d.s[2] * y2;
       part[2] += y0 * y0 + y1 * y1 + y2 * y2;
     }
-    a.g[i] = g0;
-    a.g[(size_t)N + i] = g1;
-    a.g[2 * (size_t)N + i] = g2;
+    double* go = a.g_out != nullptr ? a.g_out : a.g;
+    go[i] = g0;
+    go[(size_t)N + i] = g1;
+    go[2 * (size_t)N + i] = g2;
   }
 }
 
@@ -119,6 +123,9 @@ struct FinishIn {
   long long k, best_k, max_iter, stall_iters, evals;
   int mode, sweep;
   double bb_switch;
+  LineSearch ls;
+  int ls_trial, ls_nb;
+  double ls_C, ls_Q, ls_G;
 };
 
 __device__ __forceinline__ FinishIn load_finish_in(const MinState* st) {
@@ -134,7 +141,55 @@ __device__ __forceinline__ FinishIn load_finish_in(const MinState* st) {
   f.mode = st->mode;
   f.sweep = st->sweep;
   f.bb_switch = st->bb_switch;
+  f.ls = st->ls;
+  f.ls_trial = st->ls_trial;
+  f.ls_nb = st->ls_nb;
+  f.ls_C = st->ls_C;
+  f.ls_Q = st->ls_Q;
+  f.ls_G = st->ls_G;
   return f;
+}
+
+// BB candidate of eq. (12) for the step after update k (k >= 1): tau1 =
+// s.s / |s.y|, tau2 = |s.y| / y.y alternately by the parity of k, or
+// (bb_switch = kappa > 0) tau2 where tau2 < kappa tau1; a candidate that is
+// not finite and positive keeps tau.
+__device__ __forceinline__ double bb_step(long long k, double bb_switch, const double v[kNPartial],
+                                          double tau) {
+  const double ss = v[0], sy = fabs(v[1]), yy = v[2];
+  const double t1 = ss / sy, t2 = sy / yy;
+  const double cand = bb_switch > 0.0 ? (t2 < bb_switch * t1 ? t2 : t1) : ((k & 1) ? t1 : t2);
+  return (isfinite(cand) && cand > 0.0) ? cand : tau;
+}
+
+// End of a run after k updates with status end (1 converged, 2 max_iter,
+// 3 stalled): outside a sweep the run stops; in a sweep this field's mean
+// magnetisation and update count are recorded and the next field starts
+// from the same m (BB state, line-search state and stall tracking reset).
+__device__ __forceinline__ void end_run(MinState* st, int end, long long k,
+                                        const double v[kNPartial]) {
+  if (st->sweep == 0) {
+    st->done = end;
+    return;
+  }
+  const int fi = st->field;
+  for (int q = 0; q < 3; ++q) st->mavg_out[3 * fi + q] = v[8 + q] * st->inv_N;
+  st->iters_out[fi] = k;
+  if (end > st->worst) st->worst = end;
+  st->field = fi + 1;
+  if (fi + 1 >= st->n_fields) {
+    st->done = st->worst;
+  } else {
+    for (int q = 0; q < 3; ++q) st->H[q] = st->fields[3 * (fi + 1) + q];
+    st->k = 0;
+    st->tau = st->tau0;
+    st->last_tau = st->tau0;
+    st->best_torque = __builtin_huge_val();
+    st->best_k = 0;
+    st->ls_trial = 0;
+    st->ls_retry = 0;
+    st->ls_nb = 0;
+  }
 }
 
 // Stop rule and step size from the reduced sums v (one thread); f holds the
@@ -164,6 +219,50 @@ __device__ __forceinline__ void finish_decision(MinState* st, const FinishIn& f,
     st->done = -1;
     return;
   }
+  if (f.mode == 0 && f.ls.on) {
+    // Non-monotone line search: this evaluation is either the first of the
+    // run (the base) or a trial m(tau) from the base
+    long long k = f.k;
+    if (f.ls_trial) {
+      const double thr = f.ls_C - f.ls.rho * f.tau * (kMu0 * Ms * V) * f.ls_G;
+      if (!(E <= thr) && f.ls_nb < f.ls.max_back) {
+        // rejected: the same base, a shorter step
+        const double tau = f.tau * f.ls.sigma;
+        st->tau = tau;
+        st->last_tau = tau;
+        st->ls_nb = f.ls_nb + 1;
+        st->ls_retry = 1;
+        st->pending = 1;
+        return;
+      }
+      // accepted: the trial is the new state
+      const double Qn = f.ls.eta * f.ls_Q + 1.0;
+      st->ls_C = (f.ls.eta * f.ls_Q * f.ls_C + E) / Qn;
+      st->ls_Q = Qn;
+      k += 1;
+      st->k = k;
+      st->last_k = k;
+    } else {
+      st->ls_C = E;
+      st->ls_Q = 1.0;
+    }
+    st->ls_G = v[11];
+    st->ls_nb = 0;
+    st->ls_retry = 0;
+    int end = 0;
+    if (T < f.tol) end = 1;
+    else if (k >= f.max_iter) end = 2;
+    if (end != 0) {
+      end_run(st, end, k, v);
+      return;
+    }
+    const double tau = k > 0 ? bb_step(k, f.bb_switch, v, f.tau) : f.tau;
+    st->tau = tau;
+    st->last_tau = tau;
+    st->ls_trial = 1;
+    st->pending = 1;
+    return;
+  }
   if (f.mode == 0) {
     int end = 0;
     if (T < f.tol) end = 1;
@@ -177,38 +276,12 @@ __device__ __forceinline__ void finish_decision(MinState* st, const FinishIn& f,
       }
     }
     if (end != 0) {
-      if (f.sweep == 0) {
-        st->done = end;
-      } else {
-        // record this field, then continue with the next one from the same m
-        const int fi = st->field;
-        for (int q = 0; q < 3; ++q) st->mavg_out[3 * fi + q] = v[8 + q] * st->inv_N;
-        st->iters_out[fi] = k;
-        if (end > st->worst) st->worst = end;
-        st->field = fi + 1;
-        if (fi + 1 >= st->n_fields) {
-          st->done = st->worst;
-        } else {
-          for (int q = 0; q < 3; ++q) st->H[q] = st->fields[3 * (fi + 1) + q];
-          st->k = 0;
-          st->tau = st->tau0;
-          st->last_tau = st->tau0;
-          st->best_torque = __builtin_huge_val();
-          st->best_k = 0;
-        }
-      }
+      end_run(st, end, k, v);
       return;
     }
   }
-  double tau = f.tau;
-  if (k > 0) {
-    // eq. (12): tau1 = s.s / |s.y|, tau2 = |s.y| / y.y; alternately by the
-    // parity of k, or (bb_switch = kappa > 0) tau2 where tau2 < kappa tau1
-    const double ss = v[0], sy = fabs(v[1]), yy = v[2];
-    const double t1 = ss / sy, t2 = sy / yy;
-    const double cand = f.bb_switch > 0.0 ? (t2 < f.bb_switch * t1 ? t2 : t1) : ((k & 1) ? t1 : t2);
-    if (isfinite(cand) && cand > 0.0) tau = cand;
-  }
+  // eq. (12) for k >= 1; the first step keeps tau0
+  const double tau = k > 0 ? bb_step(k, f.bb_switch, v, f.tau) : f.tau;
   st->tau = tau;
   st->last_tau = tau;
   st->k = k + 1;

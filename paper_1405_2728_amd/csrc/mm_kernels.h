@@ -8,6 +8,15 @@ namespace mmk {
 
 constexpr double kMu0Host = 4.0e-7 * 3.14159265358979323846;
 
+// Non-monotone line search of the step (on = 0: none): Zhang-Hager weight
+// eta, sufficient-decrease factor rho, backtracking factor sigma, at most
+// max_back rejected trials per step.
+struct LineSearch {
+  int on;
+  double eta, rho, sigma;
+  int max_back;
+};
+
 // Minimiser state of one sample, resident in device memory.  Written only
 // by the step-size kernel (one thread) and read by every kernel of the
 // iteration; the host reads it when polling.
@@ -46,6 +55,17 @@ struct MinState {
   // kappa > 0 takes the short step tau2 where tau2 < kappa tau1, else tau1
   // (a ratio switch between the two steps)
   double bb_switch;
+  // Line search (ls.on): every evaluation after the first of a run is a
+  // trial m(tau) from the accepted base (ls_trial); a rejected trial is
+  // repeated from the base with a shorter step (ls_retry: the base is the
+  // saved copy ls_mbase with its gradient in g, instead of the buffer m with
+  // the last trial's gradient in ls_g2); ls_nb rejections of this step;
+  // reference value ls_C with weight ls_Q; ls_G = sum |g|^2 of the base.
+  LineSearch ls;
+  int ls_trial, ls_retry, ls_nb;
+  double ls_C, ls_Q, ls_G;
+  double* ls_mbase;
+  double* ls_g2;
 };
 
 // Conjugate-gradient state of an adjoint solve, resident in device memory.
@@ -166,6 +186,7 @@ struct LocalArgs {
   const double* m;
   const double* Hd;
   double* g;            // in: g_{k-1}; out: g_k (NULL: no g / BB sums)
+  double* g_out;        // NULL: g_k written to g; else written here (g only read)
   const double* s;      // s_{k-1} (NULL: no BB sums)
   double* Hout;         // total effective field (NULL: not written)
   double* Hex_out;      // exchange field (NULL: not written)
@@ -183,8 +204,9 @@ struct LocalArgs {
 };
 constexpr int kLocalThreads = 256;
 // per-block sums: [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext, max |g|^2,
-// sum m_x, sum m_y, sum m_z]; entry kPartMax is a maximum, the others sums
-constexpr int kNPartial = 11;
+// sum m_x, sum m_y, sum m_z, sum |g|^2]; entry kPartMax is a maximum, the
+// others sums
+constexpr int kNPartial = 12;
 constexpr int kPartMax = 7;
 int local_blocks(int N);
 void launch_local(hipStream_t s, const LocalArgs& a);
@@ -197,7 +219,8 @@ void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int 
                    const MinState* st);
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
                         long long stall_iters, int mode, const double H[3],
-                        double bb_switch = 0.0);
+                        double bb_switch = 0.0, const LineSearch* ls = nullptr,
+                        double* ls_mbase = nullptr, double* ls_g2 = nullptr);
 void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,
                         double* mavg_out, long long* iters_out, double inv_N);
 void launch_set_mode(hipStream_t s, MinState* st, int mode);

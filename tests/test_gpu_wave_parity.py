@@ -287,3 +287,92 @@ def test_zero_denominator_keeps_previous_step(torch_cuda):
     em, et, eT, eU = compare(ref, ms, taus, torques, energies)
     say("  guard: m %.2e tau %.2e torque %.2e energy %.2e" % (em, et, eT, eU))
     assert em < 1e-12 and eT < 1e-8 and eU < 1e-8
+
+
+# ---- non-monotone line search (option line_search; oracle minimize_ls) ----------
+def ls_context(torch, n, d, H, tau0, mat=(8e5, 1.3e-11, 500.0, (1, 0, 0)), n_samples=1):
+    from paper_1405_2728_amd import Context
+    ctx = Context("fp64", n_samples=n_samples)
+    ctx.set_option("line_search", 1)
+    ctx.set_option("tau0", tau0)
+    for k in range(n_samples):
+        ctx.set_geometry(k, *n, *d)
+        ctx.set_material(k, *mat)
+        ctx.set_field(k, H)
+    return ctx
+
+
+def test_line_search_iterates_match_oracle(torch_cuda):
+    """A first step far too long (tau0 = 3 / Ms): the device rejects and
+    shortens trials exactly as the oracle's line search does; accepted
+    states m_k, their steps, torques, energies and the evaluation counts
+    (rejected trials included) agree for k = 0..10 on the fused kernels."""
+    torch = torch_cuda
+    n, d = (64, 32, 2), (5e-9,) * 3
+    H = (2e4, 3e3, 0.0)
+    tau0 = 3.0 / 8e5
+    rng = np.random.default_rng(17)
+    m0 = synth.uniform_with_noise((1, 0.3, 0.1), *n, 0.2, rng)
+    P = of.Problem(*n, *d, Ms=8e5, A=1.3e-11, Ku=500.0, H_ext=H)
+    ctx = ls_context(torch, n, d, H, tau0)
+    back = 0
+    for k in range(11):
+        ref = om.minimize_ls(P, m0, tol=0.0, max_iter=k, tau0=tau0, record=True)
+        m = torch.tensor(m0, device="cuda")
+        r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=k)
+        st = ctx.last_step(0)
+        em = float(np.max(np.abs(m.cpu().numpy() - ref["m"])))
+        say("  k %d evals gpu %d oracle %d backtracks %d |dm| %.2e" % (
+            k, r["heff_evals"], ref["heff_evals"], ref["backtracks"], em))
+        assert r["iters"] == k and r["heff_evals"] == ref["heff_evals"]
+        assert em < 1e-8
+        assert abs(r["torque"] / ref["torque"] - 1) < 1e-8
+        assert abs(r["energy"] / ref["energy"] - 1) < 1e-8
+        if k > 0:
+            assert abs(st["tau"] / ref["taus"][-1] - 1) < 1e-8
+        back = ref["backtracks"]
+    ctx.close()
+    assert back >= 1            # the case exercises rejections
+
+
+def test_line_search_run_and_sweep(torch_cuda):
+    """Runs to tolerance with the line search: the device reaches the
+    oracle's state (same basin, energy 1e-9) with an evaluation count within
+    10% of the oracle's; a two-sample sweep (per-sample launches: the batched
+    form excludes the line search) equals two one-sample sweeps bit for bit
+    and follows the oracle's sweep."""
+    torch = torch_cuda
+    n, d = (64, 32, 2), (5e-9,) * 3
+    H = (2e4, 3e3, 0.0)
+    rng = np.random.default_rng(19)
+    m0 = synth.uniform_with_noise((1, 0.3, 0.1), *n, 0.2, rng)
+    P = of.Problem(*n, *d, Ms=8e5, A=1.3e-11, Ku=500.0, H_ext=H)
+    ref = om.minimize_ls(P, m0, tol=1e-7)
+    ctx = ls_context(torch, n, d, H, 1e-3 / 8e5)
+    m = torch.tensor(m0, device="cuda")
+    r = ctx.minimize_to_tol(0, m, tol=1e-7)
+    ctx.close()
+    say("  run: evals gpu %d oracle %d" % (r["heff_evals"], ref["heff_evals"]))
+    assert r["converged"] and ref["converged"]
+    mg = m.cpu().numpy()
+    assert om.torque(mg, P.heff(mg), P.Ms) < 1e-7 * 1.0001
+    assert np.max(np.abs(mg - ref["m"])) < 1e-4
+    assert abs(r["energy"] - ref["energy"]) < 1e-9 * abs(ref["energy"])
+    assert abs(r["heff_evals"] / ref["heff_evals"] - 1) < 0.1
+    # sweeps
+    F = synth.loop_fields(20.0, 5.0, synth.tilted(10.0))
+    two = ls_context(torch, n, d, H, 1e-3 / 8e5, n_samples=2)
+    ms = [torch.tensor(m0, device="cuda"), torch.tensor(m0, device="cuda")]
+    mavg2, it2, rc2 = two.hysteresis_sweep(ms, np.stack([F, F]), tol=1e-6)
+    two.close()
+    one = ls_context(torch, n, d, H, 1e-3 / 8e5)
+    m1 = torch.tensor(m0, device="cuda")
+    mavg1, it1, rc1 = one.hysteresis_sweep([m1], F, tol=1e-6)
+    one.close()
+    assert rc1 == 0 and rc2 == 0
+    assert np.array_equal(mavg2[0], mavg1[0]) and np.array_equal(mavg2[1], mavg1[0])
+    assert torch.equal(ms[0], m1) and torch.equal(ms[1], m1)
+    Q = of.Problem(*n, *d, Ms=8e5, A=1.3e-11, Ku=500.0)
+    osw = om.sweep(Q, m0, F, tol=1e-6, line_search=True)
+    say("  sweep <m> max diff %.2e" % np.max(np.abs(mavg1[0] - osw["mavg"])))
+    assert np.max(np.abs(mavg1[0] - osw["mavg"])) < 1e-3

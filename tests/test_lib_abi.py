@@ -112,6 +112,17 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"bb_switch", float("inf")) == -1
         assert lib.mm_set_option(h, b"bb_switch", 0.5) == 0
         assert lib.mm_set_option(h, b"bb_switch", 0.0) == 0
+        assert lib.mm_set_option(h, b"line_search", 2.0) == -1
+        assert lib.mm_set_option(h, b"line_search", 1.0) == 0
+        assert lib.mm_set_option(h, b"line_search", 0.0) == 0
+        assert lib.mm_set_option(h, b"ls_eta", 1.5) == -1
+        assert lib.mm_set_option(h, b"ls_eta", 0.85) == 0
+        assert lib.mm_set_option(h, b"ls_rho", 0.0) == -1
+        assert lib.mm_set_option(h, b"ls_rho", 1e-4) == 0
+        assert lib.mm_set_option(h, b"ls_sigma", 1.0) == -1
+        assert lib.mm_set_option(h, b"ls_sigma", 0.5) == 0
+        assert lib.mm_set_option(h, b"ls_max", 2.5) == -1
+        assert lib.mm_set_option(h, b"ls_max", 30.0) == 0
         assert lib.mm_set_option(h, b"rows_per_block", -1.0) == -1
         assert lib.mm_set_option(h, b"rows_per_block", 2.5) == -1
         assert lib.mm_set_option(h, b"rows_per_block", 3.0) == 0
