@@ -14,7 +14,7 @@ Follows Sec. 2 of the paper step by step:
 * stop rule: the torque max_i |g_k^i| / Ms below a tolerance.
 
 Readings (the paper is garbled or silent; each reading is listed in the
-design notes as well):
+design notes as well, under the same number):
 
 R1  Sign.  Eq. (4) equates v - (v.m)m with m x (m x v), but the identity is
     m x (m x v) = -(v - (v.m)m).  Carried into eqs. (6)/(7) the printed "+"
@@ -36,14 +36,14 @@ R8  Renormalisation after every update (eq. (7) preserves |m| exactly; this
 R9  Each field of a sweep restarts the BB state (k = 0, tau = tau0) from the
     previous field's magnetisation (Sec. 4: the previous configuration is
     the starting point).
-R10 Step switch (optional, bb_switch = kappa > 0).  Sec. 2 contrasts its
+R21 Step switch (optional, bb_switch = kappa > 0).  Sec. 2 contrasts its
     plain alternation with a more elaborate switch between the two steps
     used by Exl et al., without stating it.  The switch offered here is the
     ratio rule of adaptive BB methods: tau2 where tau2 < kappa tau1, else
     tau1, each formed with |s.y| and guarded as in R5.  Since
     (s.y)^2 <= (s.s)(y.y), tau2 <= tau1: kappa > 1 always takes tau2, a
     tiny kappa always tau1.  Parity unpinned against Exl et al.'s own rule.
-R11 Non-monotone line search (optional safeguard of the step choice; the
+R22 Non-monotone line search (optional safeguard of the step choice; the
     paper uses none).  Along the curve tau -> m(tau) of eq. (7) the energy
     falls at rate dU/dtau = -mu0 Ms V sum_i |g_i|^2 at tau = 0 (first order
     m(tau) = m - tau g, and dU/dm_i = -mu0 Ms V H_eff,i).  A trial step tau
@@ -112,7 +112,7 @@ def normalise(m):
 
 def bb_candidate(k, ss, sy, yy, bb_switch=0.0):
     """Step size of eq. (12) for iteration k >= 1 (readings R4, R5; with
-    bb_switch > 0 the ratio switch of reading R10); returns None when the
+    bb_switch > 0 the ratio switch of reading R21); returns None when the
     guard rejects the candidate."""
     with np.errstate(divide="ignore", invalid="ignore"):
         ss, sy, yy = np.float64(ss), np.float64(abs(sy)), np.float64(yy)
@@ -180,7 +180,7 @@ def minimize(problem, m0, tol=1e-6, max_iter=100000, tau0=None, record=False, bb
 
 def minimize_ls(problem, m0, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0.0,
                 eta=0.85, rho=1e-4, sigma=0.5, ls_max=30, record=False, keep_states=False):
-    """The minimiser with the non-monotone line search of reading R11.
+    """The minimiser with the non-monotone line search of reading R22.
 
     Same return dict as minimize (``iters`` = accepted updates,
     ``heff_evals`` = evaluations including rejected trials), plus
@@ -245,7 +245,7 @@ def sweep(problem, m0, fields, tol=1e-6, max_iter=100000, tau0=None, bb_switch=0
 
     ``fields`` is [n_fields, 3] in A/m.  For each field the minimiser runs
     once from the previous field's result (with ``line_search`` the
-    safeguarded form of reading R11, its reference value restarting at every
+    safeguarded form of reading R22, its reference value restarting at every
     field).  Returns per-field mean
     magnetisation <m> [n_fields, 3], iteration counts, energies and the final
     magnetisation.

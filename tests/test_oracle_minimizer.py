@@ -316,7 +316,7 @@ def test_relaxation_lowers_energy_c0_like():
     assert r["torques"][-1] < 1e-6
 
 
-# ------------------------------------------------- non-monotone line search (R11)
+# ------------------------------------------------- non-monotone line search (R22)
 def test_energy_slope_along_the_midpoint_curve():
     """dU/dtau at tau = 0 along tau -> m(tau) of eq. (7) is -mu0 Ms V sum |g|^2
     (the slope the line search's sufficient-decrease test uses), checked by a
