@@ -50,8 +50,10 @@ struct Sample {
   void* twz = nullptr;
   void* B = nullptr;          // 3-D path: spectrum after the y transform
   double* Hd = nullptr;
-  double* g = nullptr;
-  double* s = nullptr;
+  // g_k and s_k = m_{k+1} - m_k in the transform type of the context
+  // (gs_bytes per value): they feed only the step direction and the BB sums
+  void* g = nullptr;
+  void* s = nullptr;
   double* partials = nullptr;
   int nblk = 0;
   MinState* st = nullptr;
@@ -86,7 +88,7 @@ struct Sample {
   long long ref_age = 0;      // iterations since the last reference pass
   // line search: saved base state and the trial's gradient (on first use)
   double* ls_mbase = nullptr;
-  double* ls_g2 = nullptr;
+  void* ls_g2 = nullptr;      // transform type, like g
   // captured batch of poll_every minimiser iterations (use_graph), valid for
   // the m buffer, batch length, correction flag and material it was made with
   hipGraphExec_t it_graph = nullptr;
@@ -138,6 +140,12 @@ struct mm_ctx {
 namespace {
 
 bool single(const mm_ctx* c) { return c->prec == MM_MIXED; }
+// bytes per value of the g and s streams (the transform type)
+size_t gs_bytes(const mm_ctx* c) { return single(c) ? sizeof(float) : sizeof(double); }
+template <typename T>
+T* as(void* p) {
+  return static_cast<T*>(p);
+}
 
 int fail(mm_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -572,8 +580,8 @@ void enqueue_reference(mm_ctx* c, Sample& s, const double* m, const MinState* ms
   const Conv v = conv_ref(s);
   const int* done = mst ? &mst->done : nullptr;
   Timer t(c, KID_REF);
-  launch_xf<double>(st, const_cast<double*>(m), nullptr, nullptr, mst, s.nx, s.ny, s.nz, s.Px, v.R,
-                    v.spec, v.twx, nullptr, s.mref);
+  launch_xf<double>(st, const_cast<double*>(m), (const double*)nullptr, (double*)nullptr, mst,
+                    s.nx, s.ny, s.nz, s.Px, v.R, v.spec, v.twx, nullptr, s.mref);
   enqueue_demag_mid(c, s, v, done, false);
   LocalArgs a = local_args(s);
   a.m = m;
@@ -594,14 +602,17 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   if (o.spec) v.spec = o.spec;
   if (o.B) v.B = o.B;
   const bool corr = o.iterate && use_ref(c, s);
+  // g and s only where the pass may apply an update (a minimiser iteration)
+  void* gx = o.iterate ? s.g : nullptr;
+  void* sx = o.iterate ? s.s : nullptr;
   {
     Timer t(c, KID_XF);
     if (v.sp)
-      launch_xf<float>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, v.R, v.spec, v.twx,
-                       corr ? s.mref : nullptr, nullptr);
+      launch_xf<float>(st, mm, as<float>(gx), as<float>(sx), mst, s.nx, s.ny, s.nz, s.Px, v.R,
+                       v.spec, v.twx, corr ? s.mref : nullptr, nullptr);
     else
-      launch_xf<double>(st, mm, s.g, s.s, mst, s.nx, s.ny, s.nz, s.Px, v.R, v.spec, v.twx,
-                        nullptr, nullptr);
+      launch_xf<double>(st, mm, as<double>(gx), as<double>(sx), mst, s.nx, s.ny, s.nz, s.Px, v.R,
+                        v.spec, v.twx, nullptr, nullptr);
   }
   enqueue_demag_mid(c, s, v, done, true);
   LocalArgs a = local_args(s, o.unit_A, o.zeeman);
@@ -739,6 +750,8 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
       b.twx = s.rtwx;
       b.twy = s.rtwy;
       b.tstride = s.rtstride;
+      b.g = nullptr;    // no update and no BB sums in the reference pass (and
+      b.s = nullptr;    // these streams have the single-precision type)
       b.pass = 2;
       dr.push_back(b);
     }
@@ -950,12 +963,12 @@ int time_rows(mm_ctx* c, Sample& s, int R, double* us) {
   a.st = s.st_eval;
   auto pass = [&]() {
     if (sp) {
-      launch_xf<float>(st, s.Hd, s.g, s.s, s.st_eval, s.nx, s.ny, s.nz, s.Px, R, s.spec, s.twx,
-                       nullptr, nullptr);
+      launch_xf<float>(st, s.Hd, as<float>(s.g), as<float>(s.s), s.st_eval, s.nx, s.ny, s.nz,
+                       s.Px, R, s.spec, s.twx, nullptr, nullptr);
       launch_xil<float>(st, s.spec, a, s.Px, R, nullptr, s.partials, s.twx);
     } else {
-      launch_xf<double>(st, s.Hd, s.g, s.s, s.st_eval, s.nx, s.ny, s.nz, s.Px, R, s.spec,
-                        s.twx, nullptr, nullptr);
+      launch_xf<double>(st, s.Hd, as<double>(s.g), as<double>(s.s), s.st_eval, s.nx, s.ny,
+                        s.nz, s.Px, R, s.spec, s.twx, nullptr, nullptr);
       launch_xil<double>(st, s.spec, a, s.Px, R, nullptr, s.partials, s.twx);
     }
   };
@@ -1081,7 +1094,7 @@ int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
 int ensure_ls(mm_ctx* c, Sample& s) {
   if (!c->ls.on || s.ls_g2 != nullptr) return MM_OK;
   if (hipMalloc((void**)&s.ls_mbase, 3ull * s.N * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&s.ls_g2, 3ull * s.N * sizeof(double)) != hipSuccess) {
+      hipMalloc(&s.ls_g2, 3ull * s.N * gs_bytes(c)) != hipSuccess) {
     dfree(s.ls_mbase);
     dfree(s.ls_g2);
     (void)hipGetLastError();
@@ -1319,8 +1332,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
             (!full || hipMalloc(&s.B, nB * 2 * creal) == hipSuccess) &&
             (!full || hipMalloc(&s.twz, (size_t)s.Pz * 2 * creal) == hipSuccess) &&
             hipMalloc((void**)&s.Hd, 3ull * s.N * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&s.g, 3ull * s.N * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&s.s, 3ull * s.N * sizeof(double)) == hipSuccess &&
+            hipMalloc(&s.g, 3ull * s.N * gs_bytes(c)) == hipSuccess &&
+            hipMalloc(&s.s, 3ull * s.N * gs_bytes(c)) == hipSuccess &&
             hipMalloc((void**)&s.partials, npart * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&s.st, sizeof(MinState)) == hipSuccess &&
             hipMalloc((void**)&s.st_eval, sizeof(MinState)) == hipSuccess &&
@@ -1356,8 +1369,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
     return fail(c, MM_ENOMEM, "device allocation failed");
   }
   HIPCHK(c, hipMemsetAsync(s.Tt, 0, nT * creal, c->stream));
-  HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * sizeof(double), c->stream));
-  HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * gs_bytes(c), c->stream));
+  HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * gs_bytes(c), c->stream));
   launch_twiddles(c->stream, s.twx, s.Px, sp);
   launch_twiddles(c->stream, s.twy, s.Py, sp);
   if (full) launch_twiddles(c->stream, s.twz, s.Pz, sp);
@@ -1368,8 +1381,8 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
     return rc;
   }
   // the tile timing ran minimiser passes on g and s: start from zero again
-  HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * sizeof(double), c->stream));
-  HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(s.g, 0, 3ull * s.N * gs_bytes(c), c->stream));
+  HIPCHK(c, hipMemsetAsync(s.s, 0, 3ull * s.N * gs_bytes(c), c->stream));
   s.has_geom = true;
   s.has_mat = s.Ms > 0;
   s.evals_total = s.iters_total = 0;
@@ -1522,7 +1535,10 @@ int mm_minimize_step(mm_ctx* c, int sample, double* m, mm_step_info* info) {
   enqueue_iteration(c, s, m);
   {
     Timer t(c, KID_UPDATE);
-    launch_update(c->stream, m, s.g, s.s, s.N, s.st);
+    if (single(c))
+      launch_update<float>(c->stream, m, as<float>(s.g), as<float>(s.s), s.N, s.st);
+    else
+      launch_update<double>(c->stream, m, as<double>(s.g), as<double>(s.s), s.N, s.st);
   }
   launch_clear_pending(c->stream, s.st);
   HIPCHK(c, hipGetLastError());

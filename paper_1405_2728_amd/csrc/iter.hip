@@ -26,13 +26,14 @@ constexpr int kXwThreads = 768;   // launch bound of the wave-FFT x passes (R <=
 
 template <typename T, int VPT>
 __global__ void __launch_bounds__(kXsThreads)
-k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
+k_xf(double* __restrict__ m, const T* __restrict__ g, T* __restrict__ sbuf,
      const MinState* __restrict__ st, int nx, int ny, int nz, int Px, int R,
      cx<T>* __restrict__ out, const cx<T>* __restrict__ twx, const double* __restrict__ msub,
      double* __restrict__ mcopy) {
   bool upd = false, ls_upd = false, retry = false;
   double tau = 0.0;
-  double *mbase = nullptr, *g2 = nullptr;
+  double* mbase = nullptr;
+  const T* g2 = nullptr;
   if (st != nullptr) {
     if (st->done != 0) return;
     upd = st->pending != 0 && mcopy == nullptr;
@@ -40,7 +41,7 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
     ls_upd = upd && st->ls.on != 0;
     retry = st->ls_retry != 0;
     mbase = st->ls_mbase;
-    g2 = st->ls_g2;
+    g2 = static_cast<const T*>(st->ls_g2);
   }
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
@@ -69,7 +70,7 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
         if (upd) {
           double gi[3], mo[3];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) gi[c] = g[(size_t)c * N + i];
+          for (int c = 0; c < 3; ++c) gi[c] = (double)g[(size_t)c * N + i];
           if (ls_upd) {
             // line search: see the wave-FFT pass below
 #pragma unroll
@@ -77,9 +78,9 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
               if (retry) {
                 mi[c] = mbase[(size_t)c * N + i];
               } else {
-                gi[c] = g2[(size_t)c * N + i];
+                gi[c] = (double)g2[(size_t)c * N + i];
                 mbase[(size_t)c * N + i] = mi[c];
-                const_cast<double*>(g)[(size_t)c * N + i] = gi[c];
+                const_cast<T*>(g)[(size_t)c * N + i] = g2[(size_t)c * N + i];
               }
             }
           }
@@ -87,7 +88,7 @@ k_xf(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ 
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             m[(size_t)c * N + i] = mo[c];
-            sbuf[(size_t)c * N + i] = mo[c] - mi[c];
+            sbuf[(size_t)c * N + i] = (T)(mo[c] - mi[c]);
             mi[c] = mo[c];
           }
         }
@@ -183,7 +184,7 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
 #pragma unroll
       for (int c = 0; c < 3; ++c) Hd_out[(size_t)c * N + i] = hd[c];
     }
-    local_cell(a, i, hd, bb, part);
+    local_cell<T>(a, i, hd, bb, part);
   }
   bool is_max[kNPartial];
   for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
@@ -212,8 +213,8 @@ __device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
 
 // Body of the forward x pass for logical block L (rows z, y0 .. y0+R-1).
 template <typename T, int VL>
-__device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* __restrict__ g,
-                                          double* __restrict__ sbuf,
+__device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __restrict__ g,
+                                          T* __restrict__ sbuf,
                                           const MinState* __restrict__ st, int nx, int ny, int nz,
                                           int R, cx<T>* __restrict__ out,
                                           const cx<T>* __restrict__ twx, int L,
@@ -227,7 +228,8 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
   // nothing and leaves after phase 1 (the flag is the same for the block).
   int done = 0, pend = 0, ls = 0, retry = 0;
   double tau = 0.0;
-  double *mbase = nullptr, *g2 = nullptr;
+  double* mbase = nullptr;
+  const T* g2 = nullptr;
   if (st != nullptr) {
     done = st->done;
     pend = st->pending;
@@ -235,7 +237,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
     ls = st->ls.on;
     retry = st->ls_retry;
     mbase = st->ls_mbase;
-    g2 = st->ls_g2;
+    g2 = static_cast<const T*>(st->ls_g2);
   }
   const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
   // line search: the trial starts from the saved base (retry) or from the
@@ -265,7 +267,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             mi[u][c] = m[(size_t)c * N + row0 + idx];
-            gi[u][c] = g != nullptr ? g[(size_t)c * N + row0 + idx] : 0.0;
+            gi[u][c] = g != nullptr ? (double)g[(size_t)c * N + row0 + idx] : 0.0;
           }
         }
       }
@@ -281,9 +283,10 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
             if (retry) {
               mi[u][c] = mbase[(size_t)c * N + i];
             } else {
-              gi[u][c] = g2[(size_t)c * N + i];
+              const T gt = g2[(size_t)c * N + i];
+              gi[u][c] = (double)gt;
               mbase[(size_t)c * N + i] = mi[u][c];
-              const_cast<double*>(g)[(size_t)c * N + i] = gi[u][c];
+              const_cast<T*>(g)[(size_t)c * N + i] = gt;
             }
           }
         }
@@ -293,7 +296,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             m[(size_t)c * N + i] = mo[c];
-            sbuf[(size_t)c * N + i] = mo[c] - mi[u][c];
+            sbuf[(size_t)c * N + i] = (T)(mo[c] - mi[u][c]);
             mi[u][c] = mo[c];
           }
         }
@@ -368,7 +371,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const double* 
 
 template <typename T, int VL>
 __global__ void __launch_bounds__(kXwThreads)
-k_xf_w(double* __restrict__ m, const double* __restrict__ g, double* __restrict__ sbuf,
+k_xf_w(double* __restrict__ m, const T* __restrict__ g, T* __restrict__ sbuf,
        const MinState* __restrict__ st, int nx, int ny, int nz, int R,
        cx<T>* __restrict__ out, const cx<T>* __restrict__ twx, const double* __restrict__ msub,
        double* __restrict__ mcopy) {
@@ -468,7 +471,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int idx = base + u * nthr;
-        if (idx < total) fetch_cell(a, row0 + idx, bb, cin[u]);
+        if (idx < total) fetch_cell<T>(a, row0 + idx, bb, cin[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -487,7 +490,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) Hd_out[(size_t)cc * N + i] = hd[cc];
         }
-        compute_cell(a, i, hd, bb, cin[u], part);
+        compute_cell<T>(a, i, hd, bb, cin[u], part);
       }
     }
   }
@@ -515,7 +518,8 @@ __global__ void __launch_bounds__(kXwThreads)
 k_xf_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   const WorkItem it = items[blockIdx.x];
   const BatchDesc& d = descs[it.sample];
-  xf_w_body<T, VL>(d.m, d.g, d.s, d.st, d.nx, d.ny, d.nz, d.R, (cx<T>*)d.spec,
+  xf_w_body<T, VL>(d.m, static_cast<const T*>(d.g), static_cast<T*>(d.s), d.st, d.nx, d.ny,
+                   d.nz, d.R, (cx<T>*)d.spec,
                    (const cx<T>*)d.twx, it.block, d.pass == 1 ? d.mref : nullptr,
                    d.pass == 2 ? d.mref : nullptr);
 }
@@ -603,7 +607,7 @@ int rows_per_block(int M, int ny, bool single) {
 }
 
 template <typename T, int VL>
-static void xf_wave(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st,
+static void xf_wave(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st,
                     int nx, int ny, int nz, int R, void* out, const void* twx, const double* msub,
                     double* mcopy) {
   const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
@@ -626,8 +630,8 @@ static void xil_wave(hipStream_t s, const void* in, const LocalArgs& a, int R, d
 }
 
 template <typename T>
-void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
-               int ny, int nz, int Px, int R, void* out, const void* twx, const double* msub,
+void launch_xf(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st, int nx, int ny,
+               int nz, int Px, int R, void* out, const void* twx, const double* msub,
                double* mcopy) {
   const int M = Px / 2;
   switch (M) {
@@ -724,7 +728,7 @@ template void launch_x_batched<float>(hipStream_t, bool, const BatchDesc*, const
                                       int, int);
 template void launch_xf<double>(hipStream_t, double*, const double*, double*, const MinState*, int,
                                 int, int, int, int, void*, const void*, const double*, double*);
-template void launch_xf<float>(hipStream_t, double*, const double*, double*, const MinState*, int,
+template void launch_xf<float>(hipStream_t, double*, const float*, float*, const MinState*, int,
                                int, int, int, int, void*, const void*, const double*, double*);
 template void launch_xil<double>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
                                  double*, const void*);

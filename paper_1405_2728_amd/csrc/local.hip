@@ -1,5 +1,7 @@
-// Local field terms, the projected direction g, the Barzilai-Borwein sums,
-// the step-size / stop-rule kernel and the midpoint (Cayley) update.
+// The step-size / stop-rule kernel, the midpoint (Cayley) update and the
+// state kernels of the minimiser.  The local field terms, the projected
+// direction g and the Barzilai-Borwein sums (mm_iter.h) run inside the
+// inverse x pass.
 //
 // Paper references (Sec. 2):
 //   g_k = m_k x (m_k x H_eff(m_k))                           eq. (8)
@@ -14,34 +16,6 @@
 #include "mm_kernels.h"
 
 namespace mmk {
-
-// One thread per cell: H_eff = H_d + H_ex + H_an + H_ext, g = m x (m x H),
-// per-block partial sums [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext,
-// max |g|^2].
-__global__ void __launch_bounds__(kLocalThreads) k_local(LocalArgs a) {
-  __shared__ double scratch[kNPartial * (kLocalThreads / 64)];
-  if (a.done != nullptr && *a.done != 0) return;
-  if (a.Hdyn != nullptr)
-    for (int c = 0; c < 3; ++c) a.H[c] = a.Hdyn[c];
-  const int N = a.nx * a.ny * a.nz;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool bb = a.g != nullptr && a.s != nullptr && a.st != nullptr &&
-                  (a.st->k > 0 || a.st->ls_trial != 0);
-  double part[kNPartial] = {};
-  if (i < N) {
-    double hd[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) hd[c] = a.Hd[(size_t)c * N + i];
-    local_cell(a, i, hd, bb, part);
-  }
-  bool is_max[kNPartial];
-  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
-  block_reduce<kLocalThreads>(part, is_max, scratch);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int v = 0; v < kNPartial; ++v) a.partials[(size_t)blockIdx.x * kNPartial + v] = part[v];
-  }
-}
 
 // One block: reduce the per-block sums in a fixed order (each thread sums
 // rows tid, tid + T, ... with kFinishRows rows in flight), then (thread 0)
@@ -113,8 +87,9 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish_b(const BatchDesc* __
 }
 
 // Apply a pending midpoint update (eq. (7)) to m and store s = m+ - m.
-__global__ void __launch_bounds__(256) k_update(double* __restrict__ m, const double* __restrict__ g,
-                                                double* __restrict__ sb, int N,
+template <typename G>
+__global__ void __launch_bounds__(256) k_update(double* __restrict__ m, const G* __restrict__ g,
+                                                G* __restrict__ sb, int N,
                                                 const MinState* __restrict__ st) {
   if (st->done != 0 || st->pending == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,13 +99,13 @@ __global__ void __launch_bounds__(256) k_update(double* __restrict__ m, const do
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     mi[c] = m[(size_t)c * N + i];
-    gi[c] = g[(size_t)c * N + i];
+    gi[c] = (double)g[(size_t)c * N + i];
   }
   cayley_step(mi, gi, tau, mo);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     m[(size_t)c * N + i] = mo[c];
-    sb[(size_t)c * N + i] = mo[c] - mi[c];
+    sb[(size_t)c * N + i] = (G)(mo[c] - mi[c]);
   }
 }
 
@@ -166,7 +141,7 @@ __global__ void __launch_bounds__(256) k_mean_finish(const double* __restrict__ 
 
 __global__ void k_reset_state(MinState* st, double tau0, double tol, long long max_iter,
                               long long stall_iters, int mode, double hx, double hy, double hz,
-                              double bb_switch, LineSearch ls, double* ls_mbase, double* ls_g2) {
+                              double bb_switch, LineSearch ls, double* ls_mbase, void* ls_g2) {
   MinState z;
   z.tau = tau0;
   z.torque = 0.0;
@@ -231,7 +206,7 @@ __global__ void k_set_mode(MinState* st, int mode) {
 
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
                         long long stall_iters, int mode, const double H[3], double bb_switch,
-                        const LineSearch* ls, double* ls_mbase, double* ls_g2) {
+                        const LineSearch* ls, double* ls_mbase, void* ls_g2) {
   LineSearch off;
   off.on = 0;
   off.eta = off.rho = off.sigma = 0.0;
@@ -256,11 +231,6 @@ void launch_set_mode(hipStream_t s, MinState* st, int mode) {
 }
 
 int local_blocks(int N) { return (N + kLocalThreads - 1) / kLocalThreads; }
-
-void launch_local(hipStream_t s, const LocalArgs& a) {
-  const int N = a.nx * a.ny * a.nz;
-  hipLaunchKernelGGL(k_local, dim3(local_blocks(N)), dim3(kLocalThreads), 0, s, a);
-}
 
 // Many per-block sums (large grids): a first stage in which block b sums
 // rows kFinishThreads b .. kFinishThreads (b + 1) - 1 in the fixed order of
@@ -311,10 +281,14 @@ void launch_finish_batched(hipStream_t s, const BatchDesc* descs, int n_samples)
   hipLaunchKernelGGL(k_finish_b, dim3(n_samples), dim3(kFinishThreads), 0, s, descs);
 }
 
-void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
-                   const MinState* st) {
-  hipLaunchKernelGGL(k_update, dim3((N + 255) / 256), dim3(256), 0, s, m, g, sbuf, N, st);
+template <typename G>
+void launch_update(hipStream_t s, double* m, const G* g, G* sbuf, int N, const MinState* st) {
+  hipLaunchKernelGGL(k_update<G>, dim3((N + 255) / 256), dim3(256), 0, s, m, g, sbuf, N, st);
 }
+template void launch_update<double>(hipStream_t, double*, const double*, double*, int,
+                                    const MinState*);
+template void launch_update<float>(hipStream_t, double*, const float*, float*, int,
+                                   const MinState*);
 
 void launch_mean(hipStream_t s, const double* m, int N, double* partials, double* out3) {
   const int nb = (N + 255) / 256;

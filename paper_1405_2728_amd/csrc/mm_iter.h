@@ -20,6 +20,8 @@ struct CellIn {
   double ku;
 };
 
+// G: the type of the g and s streams (the transform type of the kernel).
+template <typename G>
 __device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, CellIn& d) {
   const int N = a.nx * a.ny * a.nz;
   const int x = i % a.nx;
@@ -41,10 +43,12 @@ __device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, C
                a.cz * ((nb[4] - m0) + (nb[5] - m0));
   }
   if (a.g != nullptr) {
+    const G* gp = static_cast<const G*>(a.g);
+    const G* sp = static_cast<const G*>(a.s);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      d.g[c] = bb ? a.g[(size_t)c * N + i] : 0.0;
-      d.s[c] = bb ? a.s[(size_t)c * N + i] : 0.0;
+      d.g[c] = bb ? (double)gp[(size_t)c * N + i] : 0.0;
+      d.s[c] = bb ? (double)sp[(size_t)c * N + i] : 0.0;
     }
   }
   d.ku = a.ku_map != nullptr ? a.ku_map[i] : a.ku;
@@ -53,7 +57,9 @@ __device__ __forceinline__ void fetch_cell(const LocalArgs& a, int i, bool bb, C
 // Local terms of one cell i given its demag field hd: H_eff, g = m x (m x H)
 // (written to a.g_out, or back to a.g, when a.g is set) and the partial sums
 // [s.s, s.y, y.y, m.H_d, m.H_ex, Ku (m.u)^2, m.H_ext, max |g|^2, sum m,
-// sum |g|^2].
+// sum |g|^2].  The sums and the stop test take g_k in double precision; it
+// is rounded to G only where it is stored.
+template <typename G>
 __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const double hd[3],
                                              bool bb, const CellIn& d, double part[kNPartial]) {
   const int N = a.nx * a.ny * a.nz;
@@ -102,18 +108,19 @@ __device__ __forceinline__ void compute_cell(const LocalArgs& a, int i, const do
       part[1] += d.s[0] * y0 + d.s[1] * y1 + d.s[2] * y2;
       part[2] += y0 * y0 + y1 * y1 + y2 * y2;
     }
-    double* go = a.g_out != nullptr ? a.g_out : a.g;
-    go[i] = g0;
-    go[(size_t)N + i] = g1;
-    go[2 * (size_t)N + i] = g2;
+    G* go = static_cast<G*>(a.g_out != nullptr ? a.g_out : a.g);
+    go[i] = (G)g0;
+    go[(size_t)N + i] = (G)g1;
+    go[2 * (size_t)N + i] = (G)g2;
   }
 }
 
+template <typename G>
 __device__ __forceinline__ void local_cell(const LocalArgs& a, int i, const double hd[3],
                                            bool bb, double part[kNPartial]) {
   CellIn d;
-  fetch_cell(a, i, bb, d);
-  compute_cell(a, i, hd, bb, d, part);
+  fetch_cell<G>(a, i, bb, d);
+  compute_cell<G>(a, i, hd, bb, d, part);
 }
 
 // State fields the stop rule and step choice read, loaded together with the

@@ -65,7 +65,7 @@ struct MinState {
   int ls_trial, ls_retry, ls_nb;
   double ls_C, ls_Q, ls_G;
   double* ls_mbase;
-  double* ls_g2;
+  void* ls_g2;         // values of the transform type, like g
 };
 
 // Conjugate-gradient state of an adjoint solve, resident in device memory.
@@ -83,8 +83,8 @@ struct CGState {
 // material constants.  The external field is read from st->H.
 struct BatchDesc {
   double* m;
-  double* g;
-  double* s;
+  void* g;               // g and s: values of the transform type T
+  void* s;
   void* spec;            // spectrum A[kx][z][y][c] (T complex)
   const void* Tt;        // thin-film tensor (T)
   const void* twx;       // twiddles, length Px (T complex)
@@ -185,9 +185,12 @@ void launch_finish_batched(hipStream_t s, const BatchDesc* descs, int n_samples)
 struct LocalArgs {
   const double* m;
   const double* Hd;
-  double* g;            // in: g_{k-1}; out: g_k (NULL: no g / BB sums)
-  double* g_out;        // NULL: g_k written to g; else written here (g only read)
-  const double* s;      // s_{k-1} (NULL: no BB sums)
+  // g, g_out and s hold values of the kernel's transform type (double in
+  // the double-precision form; float in the single-precision form, where
+  // they feed only the step direction and the BB sums)
+  void* g;              // in: g_{k-1}; out: g_k (NULL: no g / BB sums)
+  void* g_out;          // NULL: g_k written to g; else written here (g only read)
+  const void* s;        // s_{k-1} (NULL: no BB sums)
   double* Hout;         // total effective field (NULL: not written)
   double* Hex_out;      // exchange field (NULL: not written)
   double* Han_out;      // anisotropy field (NULL: not written)
@@ -209,18 +212,18 @@ constexpr int kLocalThreads = 256;
 constexpr int kNPartial = 12;
 constexpr int kPartMax = 7;
 int local_blocks(int N);
-void launch_local(hipStream_t s, const LocalArgs& a);
 // reduction of the per-block sums, stop rule and step choice; partials has
 // room for finish_extra_rows(nblocks) rows after the nblocks rows
 void launch_finish(hipStream_t s, double* partials, int nblocks, MinState* st, double Ms,
                    double V);
 int finish_extra_rows(int nblocks);
-void launch_update(hipStream_t s, double* m, const double* g, double* sbuf, int N,
-                   const MinState* st);
+// G: the type of the g and s streams (the context's transform type)
+template <typename G>
+void launch_update(hipStream_t s, double* m, const G* g, G* sbuf, int N, const MinState* st);
 void launch_reset_state(hipStream_t s, MinState* st, double tau0, double tol, long long max_iter,
                         long long stall_iters, int mode, const double H[3],
                         double bb_switch = 0.0, const LineSearch* ls = nullptr,
-                        double* ls_mbase = nullptr, double* ls_g2 = nullptr);
+                        double* ls_mbase = nullptr, void* ls_g2 = nullptr);
 void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n_fields,
                         double* mavg_out, long long* iters_out, double inv_N);
 void launch_set_mode(hipStream_t s, MinState* st, int mode);
@@ -230,8 +233,8 @@ int rows_per_block(int M, int ny, bool single);
 // msub (NULL: none) is subtracted from m before the transform; mcopy (NULL:
 // none) receives a copy of m, and then no pending update is applied
 template <typename T>
-void launch_xf(hipStream_t s, double* m, const double* g, double* sbuf, const MinState* st, int nx,
-               int ny, int nz, int Px, int R, void* out, const void* twx, const double* msub,
+void launch_xf(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st, int nx, int ny,
+               int nz, int Px, int R, void* out, const void* twx, const double* msub,
                double* mcopy);
 template <typename T>
 // partials: per-block sums out (NULL: none), reduced by launch_finish
