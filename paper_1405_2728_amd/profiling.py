@@ -10,6 +10,11 @@ hot path).
       plain device copy to what the same counter reports for that copy.
       The result records a hash of the HIP sources; bench.py uses it only
       while the kernels are unchanged.
+  python -m paper_1405_2728_amd.profiling sq --pmc DB --trace DB [--title T] [--cmd C]
+      occupancy and issue figures per kernel (markdown) from a run with
+      SQ_WAVES SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_INSTS_VALU SQ_INSTS_LDS
+      SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY, with the kernel durations of a
+      kernel-trace run of the same command.
 """
 
 import argparse
@@ -59,17 +64,24 @@ def kernel_stats(db):
 
 
 def counter_means(db, counter, counts=None):
-    """Mean of `counter` per kernel; `counts` (a dict), if given, receives
-    the number of dispatches per kernel."""
+    """Mean of `counter` per kernel over the dispatches of its most frequent
+    launch shape (so that the tile autotuner's timing launches of other
+    shapes do not enter the figure); `counts` (a dict), if given, receives
+    the number of those dispatches per kernel."""
     con = sqlite3.connect(db)
-    agg = defaultdict(list)
-    for name, cn, val in con.execute(
-            "select kernel_name, counter_name, value from counters_collection"):
+    agg = defaultdict(lambda: defaultdict(list))
+    for name, gx, wx, cn, val in con.execute(
+            "select kernel_name, grid_size_x, workgroup_size_x, counter_name, value "
+            "from counters_collection"):
         if cn == counter:
-            agg[short_name(name)].append(val)
-    if counts is not None:
-        counts.update({k: len(v) for k, v in agg.items()})
-    return {k: sum(v) / len(v) for k, v in agg.items()}
+            agg[short_name(name)][int(gx) // max(int(wx), 1)].append(val)
+    out = {}
+    for k, shapes in agg.items():
+        v = max(shapes.values(), key=len)
+        out[k] = sum(v) / len(v)
+        if counts is not None:
+            counts[k] = len(v)
+    return out
 
 
 def cmd_stats(a):
@@ -82,6 +94,47 @@ def cmd_stats(a):
     for k, v in sorted(st.items(), key=lambda kv: -kv[1]["total_ms"]):
         lines.append("| %s | %d | %d | %d | %.2f | %.3f |" % (k[0], k[1], k[2], v["calls"],
                                                           v["avg_us"], v["total_ms"]))
+    print("\n".join(lines))
+
+
+N_CU = 256             # compute units of the device (4 SIMDs each)
+CLOCK_HZ = 2.4e9       # peak engine clock
+
+
+def cmd_sq(a):
+    """Per kernel (its most frequent launch shape): waves, mean resident waves
+    per CU and per SIMD over the kernel's duration, VALU issue fraction per
+    SIMD, share of wave time spent waiting on memory or LDS counters, LDS
+    bank-conflict cycles per LDS instruction.  SQ_WAVE_CYCLES,
+    SQ_ACTIVE_INST_VALU and SQ_WAIT_INST_ANY count in units of 4 cycles."""
+    names = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU",
+             "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_ANY")
+    vals = {n: counter_means(a.pmc, n) for n in names}
+    dur = {k[0]: v["avg_us"] for k, v in sorted(kernel_stats(a.trace).items(),
+                                                   key=lambda kv: kv[1]["calls"])}
+    lines = ["# %s" % (a.title or os.path.basename(a.pmc)), ""]
+    if a.cmd:
+        lines += ["Commands: %s" % a.cmd, ""]
+    lines += ["Kernel time from the kernel-trace run; SQ_WAVE_CYCLES, SQ_ACTIVE_INST_VALU "
+              "and SQ_WAIT_INST_ANY in units of 4 cycles at %.1f GHz; %d CUs of 4 SIMDs." %
+              (CLOCK_HZ / 1e9, N_CU), "",
+              "| kernel | us | waves | VALU instr / wave | resident waves / CU | "
+              "per SIMD | VALU busy / SIMD | waiting share | LDS conflict cycles / LDS instr |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(vals["SQ_WAVES"], key=lambda k: -dur.get(k, 0.0)):
+        if k not in dur or dur[k] <= 0:
+            continue
+        cyc = dur[k] * 1e-6 * CLOCK_HZ
+        w = vals["SQ_WAVES"][k]
+        wc = 4 * vals["SQ_WAVE_CYCLES"].get(k, 0.0)
+        res = wc / (cyc * N_CU)
+        busy = 4 * vals["SQ_ACTIVE_INST_VALU"].get(k, 0.0) / (cyc * N_CU * 4)
+        wait = 4 * vals["SQ_WAIT_INST_ANY"].get(k, 0.0) / wc if wc else 0.0
+        lds = vals["SQ_INSTS_LDS"].get(k, 0.0)
+        conf = vals["SQ_LDS_BANK_CONFLICT"].get(k, 0.0) / lds if lds else 0.0
+        lines.append("| %s | %.2f | %d | %.0f | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
+            k, dur[k], w, vals["SQ_INSTS_VALU"].get(k, 0.0) / max(w, 1), res, res / 4, busy,
+            wait, conf))
     print("\n".join(lines))
 
 
@@ -136,9 +189,16 @@ def main(argv=None):
         t.add_argument("--cmd-" + k.replace("_", "-"), dest="cmd_" + k, default="")
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--out", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("--pmc", required=True)
+    q.add_argument("--trace", required=True)
+    q.add_argument("--title", default="")
+    q.add_argument("--cmd", default="")
     a = p.parse_args(argv)
     if a.cmd_name == "stats":
         cmd_stats(a)
+    elif a.cmd_name == "sq":
+        cmd_sq(a)
     else:
         cmd_traffic(a)
 
