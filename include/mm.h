@@ -45,7 +45,9 @@
  * Precision: MM_FP64 computes everything in double.  MM_MIXED computes the
  * demag convolution (FFT passes and tensor product) in single precision and
  * keeps double precision for the tensor set-up, the local field terms, the
- * step-size and energy reductions, the stop test and the update; its
+ * step-size and energy reductions, the stop test, the update and the state
+ * m; the previous direction g and step s, which enter only the next update
+ * and the Barzilai-Borwein sums, are stored in single precision.  Its
  * arguments are double precision as well.
  *
  * Streams: all work is ordered on the stream given to mm_create (NULL =

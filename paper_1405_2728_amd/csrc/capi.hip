@@ -2,10 +2,12 @@
 // iteration sequences, polling, sweeps, timing.  See include/mm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -125,6 +127,9 @@ struct mm_ctx {
   int rows_forced = 0;          // > 0: rows per block of the x passes (tests)
   int mixed_radix = 1;          // 1: wave lengths 64 VL (VL = 3, 5, 6, 7) where shorter
   int concurrent_groups = 1;    // batched passes: launch groups on forked streams
+  int persistent = 1;           // batched passes: one persistent launch per pass (per
+                                // layer count for yz); 0: one launch per group of
+                                // equal transform lengths
   // auxiliary streams (default priority) and fork/join events of the
   // batched passes, made on first use
   std::vector<hipStream_t> aux;
@@ -663,9 +668,19 @@ struct BatchGroup {
   int off = 0, n = 0;         // range in the item table
 };
 
+// A persistent launch: its range in the item table, block size, dynamic
+// LDS and grid, for the iteration (main) and the reference pass (ref).
+struct PersistLaunch {
+  int off = 0, n = 0, threads = 0, nz = 0;
+  size_t lds = 0, lds_ref = 0;
+  int grid = 8, grid_inv = 8, grid_ref = 8, grid_ref_inv = 8;
+};
+
 struct BatchPlan {
   std::vector<int> members;               // sample indices, in table order
   std::vector<BatchGroup> xg, yg;
+  std::vector<PersistLaunch> px;          // x passes: one per rows per block R
+  std::vector<PersistLaunch> pyz;         // yz pass: one per layer count
   BatchDesc* descs = nullptr;
   BatchDesc* descs_ref = nullptr;         // reference pass (defect correction), or NULL
   WorkItem* items = nullptr;
@@ -696,11 +711,12 @@ void xcd_order(std::vector<WorkItem>& v) {
   v.swap(o);
 }
 
-int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
+// only (optional): the samples to include (running ones), by index
+int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<char>* only = nullptr) {
   std::vector<BatchDesc> d;
   for (int k = 0; k < (int)c->smp.size(); ++k) {
     Sample& s = c->smp[k];
-    if (!batchable(c, s)) continue;
+    if (!batchable(c, s) || (only && !(*only)[k])) continue;
     BatchDesc b;
     const LocalArgs a = local_args(s);
     b.m = m[k];
@@ -785,6 +801,53 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P) {
   };
   add_groups(true, P.xg);
   add_groups(false, P.yg);
+  // persistent launches: the x blocks of the samples with R rows per block
+  // in one table per R (blocks of exactly 192 R threads); the yz columns in
+  // one table per layer count
+  const bool sp = single(c);
+  for (int R = 1; R <= 4; ++R) {
+    PersistLaunch L;
+    L.threads = 192 * R;
+    std::vector<WorkItem> v;
+    for (int i = 0; i < (int)d.size(); ++i) {
+      if (d[i].R != R) continue;
+      for (int blk = 0; blk < d[i].nb3; ++blk) v.push_back({i, blk});
+      L.lds = std::max(L.lds, x_block_lds(sp, d[i].M, R));
+      L.lds_ref = std::max(L.lds_ref, x_block_lds(false, d[i].M, R));
+    }
+    if (v.empty()) continue;
+    xcd_order(v);
+    L.off = (int)all.size();
+    L.n = (int)v.size();
+    all.insert(all.end(), v.begin(), v.end());
+    L.grid = x_persistent_grid(sp, false, L.threads, L.lds);
+    L.grid_inv = x_persistent_grid(sp, true, L.threads, L.lds);
+    if (refine) {
+      L.grid_ref = x_persistent_grid(false, false, L.threads, L.lds_ref);
+      L.grid_ref_inv = x_persistent_grid(false, true, L.threads, L.lds_ref);
+    }
+    P.px.push_back(L);
+  }
+  for (int nz = 1; nz <= 4; ++nz) {
+    PersistLaunch L;
+    L.nz = nz;
+    L.threads = 192 * nz;
+    std::vector<WorkItem> v;
+    for (int i = 0; i < (int)d.size(); ++i) {
+      if (d[i].nz != nz) continue;
+      for (int kx = 0; kx <= d[i].M; ++kx) v.push_back({i, kx});
+      L.lds = std::max(L.lds, yz_block_lds(sp, d[i].Py, nz, d[i].tstride));
+      if (refine) L.lds_ref = std::max(L.lds_ref, yz_block_lds(false, d[i].Py, nz, dr[i].tstride));
+    }
+    if (v.empty()) continue;
+    xcd_order(v);
+    L.off = (int)all.size();
+    L.n = (int)v.size();
+    all.insert(all.end(), v.begin(), v.end());
+    L.grid = yz_persistent_grid(sp, nz, L.lds);
+    if (refine) L.grid_ref = yz_persistent_grid(false, nz, L.lds_ref);
+    P.pyz.push_back(L);
+  }
   if (hipMalloc((void**)&P.descs, d.size() * sizeof(BatchDesc)) != hipSuccess ||
       (refine && hipMalloc((void**)&P.descs_ref, d.size() * sizeof(BatchDesc)) != hipSuccess) ||
       hipMalloc((void**)&P.items, all.size() * sizeof(WorkItem)) != hipSuccess) {
@@ -858,6 +921,22 @@ void for_groups(mm_ctx* c, int n, F fn) {
 void enqueue_batched_reference(mm_ctx* c, const BatchPlan& P) {
   if (!P.descs_ref) return;
   Timer t(c, KID_REF);
+  if (c->persistent) {
+    for (int inv = 0; inv < 2; ++inv) {
+      if (inv)
+        for_groups(c, (int)P.pyz.size(), [&](int i, hipStream_t st) {
+          const PersistLaunch& L = P.pyz[i];
+          launch_yz_persistent<double>(st, P.descs_ref, P.items + L.off, L.n, L.nz, L.lds_ref,
+                                       L.grid_ref);
+        });
+      for_groups(c, (int)P.px.size(), [&](int i, hipStream_t st) {
+        const PersistLaunch& L = P.px[i];
+        launch_x_persistent<double>(st, inv != 0, P.descs_ref, P.items + L.off, L.n, L.threads,
+                                    L.lds_ref, inv ? L.grid_ref_inv : L.grid_ref);
+      });
+    }
+    return;
+  }
   for_groups(c, (int)P.xg.size(), [&](int i, hipStream_t st) {
     const auto& g = P.xg[i];
     launch_x_batched<double>(st, false, P.descs_ref, P.items + g.off, g.n, g.a, g.b);
@@ -877,6 +956,39 @@ void enqueue_batched_reference(mm_ctx* c, const BatchPlan& P) {
 void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
   hipStream_t st = c->stream;
   const bool sp = single(c);
+  if (c->persistent) {
+    auto x_pass = [&](bool inv) {
+      for_groups(c, (int)P.px.size(), [&](int i, hipStream_t s) {
+        const PersistLaunch& L = P.px[i];
+        const int g = inv ? L.grid_inv : L.grid;
+        if (sp)
+          launch_x_persistent<float>(s, inv, P.descs, P.items + L.off, L.n, L.threads, L.lds, g);
+        else
+          launch_x_persistent<double>(s, inv, P.descs, P.items + L.off, L.n, L.threads, L.lds, g);
+      });
+    };
+    {
+      Timer t(c, KID_XF);
+      x_pass(false);
+    }
+    {
+      Timer t(c, KID_YZ);
+      for_groups(c, (int)P.pyz.size(), [&](int i, hipStream_t s) {
+        const PersistLaunch& L = P.pyz[i];
+        if (sp)
+          launch_yz_persistent<float>(s, P.descs, P.items + L.off, L.n, L.nz, L.lds, L.grid);
+        else
+          launch_yz_persistent<double>(s, P.descs, P.items + L.off, L.n, L.nz, L.lds, L.grid);
+      });
+    }
+    {
+      Timer t(c, KID_XIL);
+      x_pass(true);
+    }
+    Timer t(c, KID_FINISH);
+    launch_finish_batched(st, P.descs, (int)P.members.size());
+    return;
+  }
   {
     Timer t(c, KID_XF);
     for_groups(c, (int)P.xg.size(), [&](int i, hipStream_t s) {
@@ -1634,17 +1746,17 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
                        mavg + (size_t)k * n_fields * 3, its + (size_t)k * n_fields, 1.0 / s.N);
     s.ref_age = kRefStale;
   }
-  BatchPlan plan;
+  std::unique_ptr<BatchPlan> plan(new BatchPlan);
   std::vector<char> in_batch(S, 0);
   if (c->batched && S > 1) {
-    int rc = build_batch(c, m, plan);
+    int rc = build_batch(c, m, *plan);
     if (rc != MM_OK) {
       cleanup();
       return rc;
     }
-    if (plan.members.size() < 2) plan.members.clear();
-    for (int k : plan.members) in_batch[k] = 1;
-    if (!plan.members.empty() && c->concurrent_groups) {
+    if (plan->members.size() < 2) plan->members.clear();
+    for (int k : plan->members) in_batch[k] = 1;
+    if (!plan->members.empty() && c->concurrent_groups) {
       rc = ensure_aux(c);
       if (rc != MM_OK) {
         cleanup();
@@ -1653,35 +1765,36 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     }
   }
   // a captured batch of iterations is replayed when the stream allows it
-  const bool graph = c->use_graph && c->stream != nullptr && c->prof == 0 && !plan.members.empty();
+  const bool graph = c->use_graph && c->stream != nullptr && c->prof == 0 && !plan->members.empty();
   std::vector<char> running(S, 1);
   int left = S;
-  int batch_left = (int)plan.members.size();
+  int batch_left = (int)plan->members.size();
   int polls = 0;
+  bool eager = true;   // a new plan's first poll runs eagerly, later ones replay its graph
   while (left > 0) {
     if (batch_left > 0) {
       // the first batch runs eagerly (kernel attributes are set there); later
       // batches replay one captured graph of poll_every iterations
-      if (graph && polls > 0) {
-        if (!plan.graph) {
+      if (graph && !eager) {
+        if (!plan->graph) {
           hipGraph_t g = nullptr;
           hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
           if (e == hipSuccess) {
-            enqueue_batched_reference(c, plan);
-            for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
+            enqueue_batched_reference(c, *plan);
+            for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, *plan);
             e = hipStreamEndCapture(c->stream, &g);
           }
-          if (e == hipSuccess) e = hipGraphInstantiate(&plan.graph, g, nullptr, nullptr, 0);
+          if (e == hipSuccess) e = hipGraphInstantiate(&plan->graph, g, nullptr, nullptr, 0);
           if (g) (void)hipGraphDestroy(g);
           if (e != hipSuccess) {
             cleanup();
             return fail(c, MM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
           }
         }
-        SWEEP_CHK(hipGraphLaunch(plan.graph, c->stream));
+        SWEEP_CHK(hipGraphLaunch(plan->graph, c->stream));
       } else {
-        enqueue_batched_reference(c, plan);
-        for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, plan);
+        enqueue_batched_reference(c, *plan);
+        for (int q = 0; q < c->poll_every; ++q) enqueue_batched_iteration(c, *plan);
       }
     }
     for (int k = 0; k < S; ++k) {
@@ -1689,6 +1802,7 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
       for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, c->smp[k], m[k]);
     }
     ++polls;
+    eager = false;
     hipError_t e = hipGetLastError();
     for (int k = 0; k < S && e == hipSuccess; ++k)
       if (running[k])
@@ -1706,6 +1820,24 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
         --left;
         if (in_batch[k]) --batch_left;
       }
+    // once a quarter of the batch has finished, the tables are rebuilt from
+    // the samples still running (and the graph captured again), so that the
+    // launches stop walking finished samples' blocks; results do not change,
+    // every sample's blocks and reductions being its own
+    if (batch_left >= 2 && 4 * batch_left <= 3 * (int)plan->members.size()) {
+      std::unique_ptr<BatchPlan> np(new BatchPlan);
+      const int rc = build_batch(c, m, *np, &running);
+      if (rc != MM_OK) {
+        cleanup();
+        return rc;
+      }
+      if (np->members.size() < 2) np->members.clear();
+      std::fill(in_batch.begin(), in_batch.end(), 0);
+      for (int k : np->members) in_batch[k] = 1;
+      batch_left = (int)np->members.size();
+      plan.swap(np);
+      eager = true;
+    }
   }
   std::vector<long long> ih((size_t)S * n_fields);
   SWEEP_CHK(hipMemcpyAsync(m_avg, mavg, nf3 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1770,6 +1902,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->mixed_radix = value != 0.0;
   } else if (!std::strcmp(key, "concurrent_groups")) {
     c->concurrent_groups = value != 0.0;
+  } else if (!std::strcmp(key, "persistent")) {
+    c->persistent = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
   } else if (!std::strcmp(key, "rows_per_block")) {
@@ -1847,6 +1981,7 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
   const Sample& s = c->smp[sample];
   const double sr = single(c) ? 4.0 : 8.0;
   const double N3 = 3.0 * s.N * 8.0;                                  // one [3][N] double array
+  const double G3 = 3.0 * s.N * sr;                                   // g or s (transform type)
   const double spec = (double)(s.M + 1) * 3 * s.nz * s.ny * 2 * sr;   // spectrum A
   const double trows = s.path == PATH_3D ? (double)(s.Py / 2 + 1) : 1.0;
   const double tens = (double)(s.M + 1) * trows * s.tstride * sr;
@@ -1862,11 +1997,11 @@ int mm_kernel_bytes(mm_ctx* c, int sample, int id, double* bytes) {
   const double mid64 = thin ? 2 * spec64 + tens64 : 2 * spec64 + 4 * bsp64 + tens64;
   double b = 0;
   switch (id) {
-    case KID_XF: b = 4 * N3 + spec + corr; break;   // m, g in; m, s out; spectrum out
+    case KID_XF: b = 2 * N3 + 2 * G3 + spec + corr; break;   // m, g in; m, s out; spectrum out
     case KID_YZ: b = thin ? 2 * spec + tens : 0; break;   // spectrum in/out; tensor in
-    case KID_XIL: b = spec + 4 * N3 + ku + corr; break;   // spectrum, m, g, s in; g out
+    case KID_XIL: b = spec + N3 + 3 * G3 + ku + corr; break;   // spectrum, m, g, s in; g out
     case KID_REF: b = s.has_ref ? 4 * N3 + 2 * spec64 + mid64 + ku : 0; break;
-    case KID_UPDATE: b = 4 * N3; break;             // m, g in; m, s out
+    case KID_UPDATE: b = 2 * N3 + 2 * G3; break;    // m, g in; m, s out
     case KID_Y3F: b = thin ? 0 : spec + bsp; break; // spectrum in, y spectrum out
     case KID_Z3: b = thin ? 0 : 2 * bsp + tens; break;    // y spectrum in/out; tensor in
     case KID_Y3I: b = thin ? 0 : bsp + spec; break;

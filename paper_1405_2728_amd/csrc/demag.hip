@@ -284,14 +284,17 @@ __device__ __forceinline__ void tensor_term(const T* __restrict__ t, T sy, T sz,
 
 // complex elements of one wave's slice: the transposes of the wave FFT
 // (72 VL) and the 8 slots of 64 lanes
+__host__ __device__ constexpr int yz_slice_of(int VL) { return VL * 72 > 512 ? VL * 72 : 512; }
 template <int VL>
-__host__ __device__ constexpr int yz_slice() { return VL * 72 > 512 ? VL * 72 : 512; }
+__host__ __device__ constexpr int yz_slice() { return yz_slice_of(VL); }
 
-// bytes of LDS of one yz block
+// bytes of LDS of one yz block (real type of `real` bytes)
+__host__ __device__ constexpr size_t yz_lds_of(int real, int VL, int NZ, int tstride) {
+  return (size_t)3 * NZ * yz_slice_of(VL) * 2 * real + ((size_t)tstride * real + 1023) / 1024 * 1024;
+}
 template <typename T, int VL, int NZ>
 __host__ __device__ constexpr size_t yz_lds_bytes(int tstride) {
-  return (size_t)3 * NZ * yz_slice<VL>() * sizeof(cx<T>) +
-         ((size_t)tstride * sizeof(T) + 1023) / 1024 * 1024;
+  return yz_lds_of((int)sizeof(T), VL, NZ, tstride);
 }
 
 // Every output layer of one position: dst[(zo 3 + c) SL] = scale
@@ -350,8 +353,9 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
   T* tl = reinterpret_cast<T*>(smem + (size_t)NW * SL * sizeof(cx<T>));
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int tid = thread_index();
+  const int lane = tid & 63;
+  const int w = tid >> 6;
   const int z = w / 3, c = w - 3 * (w / 3);
   cx<T>* slice = sm + w * SL;
   cx<T>* Ak = A + (size_t)kx * 3 * NZ * ny;
@@ -434,14 +438,44 @@ k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int ts
   yz_wave_body<T, VL, NZ>(A, ny, M, Tt, tstride, scale, twy, done, blockIdx.x);
 }
 
+// Column kx of sample d.
+template <typename T, int VL, int NZ>
+__device__ __forceinline__ void yz_desc(const BatchDesc& d, int kx) {
+  yz_wave_body<T, VL, NZ>((cx<T>*)d.spec, d.ny, d.M, (const T*)d.Tt, d.tstride, (T)d.scale,
+                          (const cx<T>*)d.twy, &d.st->done, kx);
+}
+
 // Batched: items[b] = (sample, kx), kx <= M; all samples share Py and nz.
 template <typename T, int VL, int NZ>
 __global__ void __launch_bounds__(192 * NZ, yz_waves_per_eu<T>())
 k_yz_wave_b(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   const WorkItem it = items[blockIdx.x];
-  const BatchDesc& d = descs[it.sample];
-  yz_wave_body<T, VL, NZ>((cx<T>*)d.spec, d.ny, d.M, (const T*)d.Tt, d.tstride, (T)d.scale,
-                          (const cx<T>*)d.twy, &d.st->done, it.block);
+  yz_desc<T, VL, NZ>(descs[it.sample], it.block);
+}
+
+// Persistent batched: one launch covers the columns of every sample with nz
+// layers, whatever its y length Py = 64 VL; each block takes its static
+// share of the table (persist_loop) and branches on the item's sample
+// length.
+template <typename T, int NZ>
+__global__ void __launch_bounds__(192 * NZ, yz_waves_per_eu<T>())
+k_yz_wave_p(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+            int n_items) {
+  persist_loop(n_items, [&](int v) {
+    const WorkItem it = items[v];
+    const BatchDesc& d = descs[it.sample];
+    switch (d.Py >> 6) {
+      case 1: yz_desc<T, 1, NZ>(d, it.block); break;
+      case 2: yz_desc<T, 2, NZ>(d, it.block); break;
+      case 3: yz_desc<T, 3, NZ>(d, it.block); break;
+      case 4: yz_desc<T, 4, NZ>(d, it.block); break;
+      case 5: yz_desc<T, 5, NZ>(d, it.block); break;
+      case 6: yz_desc<T, 6, NZ>(d, it.block); break;
+      case 7: yz_desc<T, 7, NZ>(d, it.block); break;
+      case 8: yz_desc<T, 8, NZ>(d, it.block); break;
+      default: break;
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -641,6 +675,54 @@ void launch_yz_batched(hipStream_t s, const BatchDesc* descs, const WorkItem* it
   }
 }
 
+template <typename T, int NZ>
+static const void* yzp_kernel() {
+  return (const void*)k_yz_wave_p<T, NZ>;
+}
+
+template <typename T>
+static const void* yzp_kernel_nz(int nz) {
+  switch (nz) {
+    case 1: return yzp_kernel<T, 1>();
+    case 2: return yzp_kernel<T, 2>();
+    case 3: return yzp_kernel<T, 3>();
+    default: return yzp_kernel<T, 4>();
+  }
+}
+
+size_t yz_block_lds(bool single, int Py, int nz, int tstride) {
+  return yz_lds_of(single ? 4 : 8, Py / 64, nz, tstride);
+}
+
+int yz_persistent_grid(bool single, int nz, size_t lds) {
+  const void* k = single ? yzp_kernel_nz<float>(nz) : yzp_kernel_nz<double>(nz);
+  if (lds > 48 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 192 * nz, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 8;
+  }
+  const int g = per_cu * cus / 8 * 8;
+  return g < 8 ? 8 : g;
+}
+
+template <typename T>
+void launch_yz_persistent(hipStream_t s, const BatchDesc* descs, const WorkItem* items,
+                          int n_items, int nz, size_t lds, int grid) {
+  const int g = n_items < grid ? n_items : grid;
+  if (g <= 0) return;
+  const void* k = yzp_kernel_nz<T>(nz);
+  if (lds > 48 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  void* args[] = {(void*)&descs, (void*)&items, (void*)&n_items};
+  (void)hipLaunchKernel(k, dim3(g), dim3(192 * nz), args, lds, s);
+}
+
+template void launch_yz_persistent<double>(hipStream_t, const BatchDesc*, const WorkItem*, int,
+                                           int, size_t, int);
+template void launch_yz_persistent<float>(hipStream_t, const BatchDesc*, const WorkItem*, int, int,
+                                          size_t, int);
 template void launch_yz_batched<double>(hipStream_t, const BatchDesc*, const WorkItem*, int, int,
                                         int, int);
 template void launch_yz_batched<float>(hipStream_t, const BatchDesc*, const WorkItem*, int, int,

@@ -207,8 +207,9 @@ k_xil(const cx<T>* __restrict__ in, LocalArgs a, int Px, int R, double* __restri
 // that the 3 R regions read or written at one kx (one per lane of a chunk)
 // start on different LDS banks.
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int wx_region_of(int VL) { return VL * 72 + 11; }
 template <int VL>
-__host__ __device__ constexpr int wx_region() { return VL * 72 + 11; }
+__host__ __device__ constexpr int wx_region() { return wx_region_of(VL); }
 __device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
 
 // Body of the forward x pass for logical block L (rows z, y0 .. y0+R-1).
@@ -252,13 +253,17 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
   const int y0 = (L - z * nyb) * R;
   const int rows = min(R, ny - y0);
   const int N = nx * ny * nz;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = thread_index(), nthr = 192 * R;
+  // the row-parallel loops take 192 R threads (a persistent launch may have
+  // more: they only join the barriers), so that every cell is summed by the
+  // same thread as in a launch of exactly 192 R threads
+  const int first = tid < nthr ? tid : (1 << 30);
   // phase 1: pending update of the rows, sequences into LDS (x = 2j + h -> re/im of j)
   {
     constexpr int U = 4;                       // cells in flight per thread
     const int total = rows * nx;
     const size_t row0 = ((size_t)z * ny + y0) * nx;   // rows of the block are contiguous
-    for (int base = tid; base < total; base += U * nthr) {
+    for (int base = first; base < total; base += U * nthr) {
       double mi[U][3], gi[U][3];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -317,7 +322,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
   if (done != 0) return;
   // zero padding x in [nx, 2M)
   const int jz = nx >> 1;   // first complex slot holding padding (its .y if nx is odd)
-  for (int idx = tid; idx < rows * 3 * (M - jz); idx += nthr) {
+  for (int idx = first; idx < rows * 3 * (M - jz); idx += nthr) {
     const int q = idx / (M - jz), j = jz + idx - q * (M - jz);
     if (2 * j >= nx) sm[(size_t)q * RG + j] = mk(T(0), T(0));
     else smr[2 * ((size_t)q * RG + j) + 1] = T(0);          // x = nx - 1 even: .y is padding
@@ -363,7 +368,7 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
   const size_t slab = (size_t)3 * nz * ny;
   const int q3 = 3 * rows;
   cx<T>* dst = out + ((size_t)z * ny + y0) * 3;
-  for (int idx = tid; idx < (M + 1) * q3; idx += nthr) {
+  for (int idx = first; idx < (M + 1) * q3; idx += nthr) {
     const int k = idx / q3, q = idx - k * q3;
     dst[(size_t)k * slab + q] = sm[(size_t)q * RG + wx_pad(k)];
   }
@@ -404,7 +409,11 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   const int y0 = (L - z * nyb) * R;
   const int rows = min(R, ny - y0);
   const int N = nx * ny * nz;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = thread_index(), nthr = 192 * R;
+  // the row-parallel loops take 192 R threads (a persistent launch may have
+  // more: they only join the barriers), so that every cell is summed by the
+  // same thread as in a launch of exactly 192 R threads
+  const int first = tid < nthr ? tid : (1 << 30);
   // phase 1: spectrum chunks into LDS
   const size_t slab = (size_t)3 * nz * ny;
   const int q3 = 3 * rows;
@@ -412,7 +421,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   {
     constexpr int U = 8;                       // loads in flight per thread
     const int total = (M + 1) * q3;
-    for (int base = tid; base < total; base += U * nthr) {
+    for (int base = first; base < total; base += U * nthr) {
       T re[U], im[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -466,7 +475,7 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
     constexpr int U = 1;                       // cells per thread per round
     const int total = rows * nx;
     const int row0 = (z * ny + y0) * nx;
-    for (int base = tid; base < total; base += U * nthr) {
+    for (int base = first; base < total; base += U * nthr) {
       CellIn cin[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -513,22 +522,24 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
 // ---- batched passes: one launch covers the blocks of several samples ---------
 // items[b] names the sample and its logical block; every sample of a launch
 // has the same transform length and rows per block.
+// Logical block `block` of sample d's forward x pass.
 template <typename T, int VL>
-__global__ void __launch_bounds__(kXwThreads)
-k_xf_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
-  const WorkItem it = items[blockIdx.x];
-  const BatchDesc& d = descs[it.sample];
+__device__ __forceinline__ void xf_desc(const BatchDesc& d, int block) {
   xf_w_body<T, VL>(d.m, static_cast<const T*>(d.g), static_cast<T*>(d.s), d.st, d.nx, d.ny,
-                   d.nz, d.R, (cx<T>*)d.spec,
-                   (const cx<T>*)d.twx, it.block, d.pass == 1 ? d.mref : nullptr,
-                   d.pass == 2 ? d.mref : nullptr);
+                   d.nz, d.R, (cx<T>*)d.spec, (const cx<T>*)d.twx, block,
+                   d.pass == 1 ? d.mref : nullptr, d.pass == 2 ? d.mref : nullptr);
 }
 
 template <typename T, int VL>
 __global__ void __launch_bounds__(kXwThreads)
-k_xil_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+k_xf_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   const WorkItem it = items[blockIdx.x];
-  const BatchDesc& d = descs[it.sample];
+  xf_desc<T, VL>(descs[it.sample], it.block);
+}
+
+// Logical block `block` of sample d's inverse x pass with its local terms.
+template <typename T, int VL>
+__device__ __forceinline__ void xil_desc(const BatchDesc& d, int block) {
   LocalArgs a;
   a.m = d.m;
   a.Hd = nullptr;
@@ -562,11 +573,55 @@ k_xil_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items
     a.s = nullptr;
     a.st = nullptr;
     xil_w_body<T, VL>((const cx<T>*)d.spec, a, d.R, d.hdref, nullptr, (const cx<T>*)d.twx,
-                      it.block);
+                      block);
     return;
   }
   xil_w_body<T, VL>((const cx<T>*)d.spec, a, d.R, nullptr, d.partials, (const cx<T>*)d.twx,
-                    it.block);
+                    block);
+}
+
+template <typename T, int VL>
+__global__ void __launch_bounds__(kXwThreads)
+k_xil_wb(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  const WorkItem it = items[blockIdx.x];
+  xil_desc<T, VL>(descs[it.sample], it.block);
+}
+
+// ---- persistent batched x passes ------------------------------------------------
+// One launch covers the blocks of every sample, whatever its transform length
+// M = 64 VL: the grid holds the blocks that stay resident together and each
+// block takes its static share of the table (persist_loop) and branches on
+// the item's sample length.  A sample's rows per block R may be
+// below the launch's blockDim.x / 192 (the surplus waves then skip the
+// transform).
+template <typename T, bool INV>
+__device__ __forceinline__ void x_item(const BatchDesc& d, int block) {
+  switch (d.M >> 6) {
+#define MMK_X_CASE(V)                          \
+  case V:                                      \
+    if (INV) xil_desc<T, V>(d, block);         \
+    else xf_desc<T, V>(d, block);              \
+    break;
+    MMK_X_CASE(1)
+    MMK_X_CASE(2)
+    MMK_X_CASE(3)
+    MMK_X_CASE(4)
+    MMK_X_CASE(5)
+    MMK_X_CASE(6)
+    MMK_X_CASE(7)
+    MMK_X_CASE(8)
+#undef MMK_X_CASE
+    default: break;
+  }
+}
+
+template <typename T, bool INV>
+__global__ void __launch_bounds__(kXwThreads)
+k_x_wp(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items, int n_items) {
+  persist_loop(n_items, [&](int v) {
+    const WorkItem it = items[v];
+    x_item<T, INV>(descs[it.sample], it.block);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -707,6 +762,43 @@ static void xb_launch(hipStream_t s, bool inverse, const BatchDesc* descs, const
   }
 }
 
+// Blocks of a persistent x launch that stay resident together (a multiple
+// of 8, at least 8).
+int x_persistent_grid(bool single, bool inverse, int threads, size_t lds) {
+  const void* k = single ? (inverse ? (const void*)k_x_wp<float, true> : (const void*)k_x_wp<float, false>)
+                         : (inverse ? (const void*)k_x_wp<double, true> : (const void*)k_x_wp<double, false>);
+  if (lds > 48 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 8;
+  }
+  const int g = per_cu * cus / 8 * 8;
+  return g < 8 ? 8 : g;
+}
+
+template <typename T>
+void launch_x_persistent(hipStream_t s, bool inverse, const BatchDesc* descs,
+                         const WorkItem* items, int n_items, int threads, size_t lds, int grid) {
+  const int g = n_items < grid ? n_items : grid;
+  if (g <= 0) return;
+  if (inverse) {
+    auto k = k_x_wp<T, true>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(g), dim3(threads), lds, s, descs, items, n_items);
+  } else {
+    auto k = k_x_wp<T, false>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(g), dim3(threads), lds, s, descs, items, n_items);
+  }
+}
+
+size_t x_block_lds(bool single, int M, int R) {
+  return (size_t)3 * R * wx_region_of(M / 64) * (single ? 8 : 16);
+}
+
 template <typename T>
 void launch_x_batched(hipStream_t s, bool inverse, const BatchDesc* descs, const WorkItem* items,
                       int n_items, int M, int R) {
@@ -724,6 +816,10 @@ void launch_x_batched(hipStream_t s, bool inverse, const BatchDesc* descs, const
 
 template void launch_x_batched<double>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
                                        int, int);
+template void launch_x_persistent<double>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
+                                          int, size_t, int);
+template void launch_x_persistent<float>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
+                                         int, size_t, int);
 template void launch_x_batched<float>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
                                       int, int);
 template void launch_xf<double>(hipStream_t, double*, const double*, double*, const MinState*, int,

@@ -10,6 +10,30 @@ namespace mmk {
 
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
 
+// Work loop of a persistent kernel over the items 0 .. n-1 of an XCD-ordered
+// table: block b runs the items b, b + G, b + 2G, ... (G = gridDim.x, a
+// multiple of 8 when below n, so that every item runs on the XCD its table
+// position gives it).  A static share: a shared work counter costs each item
+// an atomic round trip on its critical path.
+template <typename F>
+__device__ __forceinline__ void persist_loop(int n, F&& item) {
+  for (int v = (int)blockIdx.x; v < n; v += (int)gridDim.x) {
+    item(v);
+    __syncthreads();   // the next item may reuse the LDS
+  }
+}
+
+// threadIdx.x through an empty asm statement that the compiler must assume
+// changes it: the persistent batched kernels run a pass body once per work
+// item in a loop, and without this the compiler hoists every body's
+// thread-index arithmetic (for all transform lengths at once) out of the
+// loop and runs out of registers.
+__device__ __forceinline__ int thread_index() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
   T x, y;

@@ -180,6 +180,20 @@ template <typename T>
 void launch_yz_batched(hipStream_t s, const BatchDesc* descs, const WorkItem* items, int n_items,
                        int Py, int nz, int tstride);
 void launch_finish_batched(hipStream_t s, const BatchDesc* descs, int n_samples);
+// persistent batched passes: one launch covers the items of every sample,
+// whatever its transform length (x: items of samples with R <= threads / 192;
+// yz: samples with nz layers); grid: blocks resident together (a multiple of
+// 8), lds: the largest block's dynamic LDS
+int x_persistent_grid(bool single, bool inverse, int threads, size_t lds);
+size_t x_block_lds(bool single, int M, int R);
+template <typename T>
+void launch_x_persistent(hipStream_t s, bool inverse, const BatchDesc* descs,
+                         const WorkItem* items, int n_items, int threads, size_t lds, int grid);
+int yz_persistent_grid(bool single, int nz, size_t lds);
+size_t yz_block_lds(bool single, int Py, int nz, int tstride);
+template <typename T>
+void launch_yz_persistent(hipStream_t s, const BatchDesc* descs, const WorkItem* items,
+                          int n_items, int nz, size_t lds, int grid);
 
 // ---- local terms, step size, update -----------------------------------------
 struct LocalArgs {

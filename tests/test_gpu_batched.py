@@ -1,8 +1,11 @@
-"""Batched sweeps: several samples of different shapes share launches (one
-per group of equal transform lengths) and run their field lists on the
-device.  The batched kernels run the same per-block code with the same
-reduction order as the per-sample path, so the results must be bitwise
-identical to it; replays of a captured graph likewise.  "mixed" is the
+"""Batched sweeps: several samples of different shapes share launches and
+run their field lists on the device.  By default each pass is one
+persistent launch covering every sample whatever its transform length (the
+yz pass one launch per layer count); the "persistent" option 0 gives one
+launch per group of equal lengths instead.  The batched kernels run the
+same per-block code with the same reduction order as the per-sample path,
+so the results must be bitwise identical to it; replays of a captured graph
+likewise.  "mixed" is the
 single-precision form with its defect correction (a double-precision
 reference pass every poll_every iterations, batched like the iteration);
 "mixed_plain" is the form without it."""
@@ -41,11 +44,12 @@ SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (
 
 
 def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent=True,
-        bb_switch=0.0):
+        bb_switch=0.0, persistent=True):
     from paper_1405_2728_amd import Context
     stream = torch.cuda.Stream() if graph else None
     ctx = Context("mixed" if prec == "mixed_plain" else prec, n_samples=len(shapes), stream=stream)
     ctx.set_option("concurrent_groups", 1 if concurrent else 0)
+    ctx.set_option("persistent", 1 if persistent else 0)
     if prec == "mixed_plain":
         ctx.set_option("refine", 0)
     ctx.set_option("batched", 1 if batched else 0)
@@ -186,6 +190,21 @@ def test_concurrent_groups_equal_serial(torch_cuda, prec):
     say("case concurrent groups", prec)
     a = run(torch, prec, batched=True, graph=True, concurrent=False)
     b = run(torch, prec, batched=True, graph=True, concurrent=True)
+    assert a[2] == b[2]
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_persistent_equals_grouped(torch_cuda, prec):
+    """One persistent launch per pass gives the same bits as one launch per
+    group of equal transform lengths (same blocks, same reductions)."""
+    torch = torch_cuda
+    say("case persistent vs grouped", prec)
+    a = run(torch, prec, batched=True, graph=True, persistent=False)
+    b = run(torch, prec, batched=True, graph=True, persistent=True)
     assert a[2] == b[2]
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])
