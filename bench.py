@@ -16,9 +16,10 @@ cells (full 3-D demag path, random start, 60 mT at 2 degrees from z).
 
 The line also carries "batched": 64 uneven thin platelets (64..256 x
 32..128 x 1..2 cells) swept through every 10th field of their +-40 mT loop,
-once with all samples sharing launches (captured graph) and once sample by
-sample, both in FP64: summed minimiser iterations per second and the
-speed-up.  --workload batched runs that alone on the whole loop (81 fields);
+once with all samples sharing launches (one persistent launch per pass,
+covering every transform length; captured graph) and once sample by sample,
+both in FP64: summed minimiser iterations per second, the speed-up and the
+HBM fraction of the samples' algorithmic bytes.  --workload batched runs that alone on the whole loop (81 fields);
 --workload adjoint times the implicit gradient of the 200 x 100 x 2 film
 with a per-cell Ku map (conjugate gradients + parameter gradients);
 --workload loop runs whole hysteresis loops (one device-driven sweep each):
