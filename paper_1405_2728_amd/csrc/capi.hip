@@ -681,6 +681,7 @@ struct BatchPlan {
   std::vector<BatchGroup> xg, yg;
   std::vector<PersistLaunch> px;          // x passes: one per rows per block R
   std::vector<PersistLaunch> pyz;         // yz pass: one per layer count
+  PersistLaunch p3[3];                    // 3-D samples: y forward, z, y inverse
   BatchDesc* descs = nullptr;
   BatchDesc* descs_ref = nullptr;         // reference pass (defect correction), or NULL
   WorkItem* items = nullptr;
@@ -694,8 +695,11 @@ struct BatchPlan {
 };
 
 bool batchable(const mm_ctx* c, const Sample& s) {
-  return !c->ls.on && s.path == PATH_THIN && s.M % 64 == 0 && s.M >= 64 && s.M <= 512 &&
-         yz_wave_ok(s.nz, s.Py) && (!single(c) || !c->refine || s.has_ref);
+  if (c->ls.on || s.M % 64 != 0 || s.M < 64 || s.M > 512) return false;
+  if (single(c) && c->refine && !s.has_ref) return false;
+  if (s.path == PATH_THIN) return yz_wave_ok(s.nz, s.Py);
+  // the 3-D stages have persistent batched launches only
+  return s.path == PATH_3D && c->persistent;
 }
 
 // XCD-aware order: hardware block b takes logical item xcd_remap(b, n), so
@@ -726,6 +730,10 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
     b.Tt = s.Tt;
     b.twx = s.twx;
     b.twy = s.twy;
+    const bool full = s.path == PATH_3D;
+    b.B = full ? s.B : nullptr;
+    b.twz = full ? s.twz : nullptr;
+    b.Pz = full ? s.Pz : 1;
     b.st = s.st;
     b.partials = s.partials;
     b.ku_map = s.ku_map;
@@ -743,7 +751,7 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
     b.ku = a.ku;
     b.kan = a.kan;
     for (int q = 0; q < 3; ++q) b.u[q] = a.u[q];
-    b.scale = -s.Ms / ((double)s.M * (double)s.Py);
+    b.scale = -s.Ms / ((double)s.M * (double)s.Py * (double)b.Pz);
     b.Ms = s.Ms;
     b.V = s.V;
     const bool corr = use_ref(c, s);
@@ -766,6 +774,10 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
       b.twx = s.rtwx;
       b.twy = s.rtwy;
       b.tstride = s.rtstride;
+      if (b.B) {
+        b.B = s.rB;
+        b.twz = s.rtwz;
+      }
       b.g = nullptr;    // no update and no BB sums in the reference pass (and
       b.s = nullptr;    // these streams have the single-precision type)
       b.pass = 2;
@@ -777,6 +789,7 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
     std::vector<BatchGroup> keys;
     for (int i = 0; i < (int)d.size(); ++i) {
       BatchGroup g;
+      if (!x && d[i].B) continue;    // 3-D samples: persistent launches only
       if (x) { g.a = d[i].M; g.b = d[i].R; }
       else { g.a = d[i].Py; g.b = d[i].nz; g.t = d[i].tstride; }
       bool seen = false;
@@ -787,7 +800,8 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
       std::vector<WorkItem> v;
       for (int i = 0; i < (int)d.size(); ++i) {
         const bool match = x ? (d[i].M == g.a && d[i].R == g.b)
-                             : (d[i].Py == g.a && d[i].nz == g.b && d[i].tstride == g.t);
+                             : (!d[i].B && d[i].Py == g.a && d[i].nz == g.b &&
+                                d[i].tstride == g.t);
         if (!match) continue;
         const int nb = x ? d[i].nb3 : d[i].M + 1;   // yz: one block per column kx = 0..M
         for (int blk = 0; blk < nb; ++blk) v.push_back({i, blk});
@@ -834,7 +848,7 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
     L.threads = 192 * nz;
     std::vector<WorkItem> v;
     for (int i = 0; i < (int)d.size(); ++i) {
-      if (d[i].nz != nz) continue;
+      if (d[i].nz != nz || d[i].B) continue;
       for (int kx = 0; kx <= d[i].M; ++kx) v.push_back({i, kx});
       L.lds = std::max(L.lds, yz_block_lds(sp, d[i].Py, nz, d[i].tstride));
       if (refine) L.lds_ref = std::max(L.lds_ref, yz_block_lds(false, d[i].Py, nz, dr[i].tstride));
@@ -847,6 +861,27 @@ int build_batch(mm_ctx* c, double* const* m, BatchPlan& P, const std::vector<cha
     L.grid = yz_persistent_grid(sp, nz, L.lds);
     if (refine) L.grid_ref = yz_persistent_grid(false, nz, L.lds_ref);
     P.pyz.push_back(L);
+  }
+  // 3-D samples: forward y, z with the tensor product, inverse y
+  for (int st = 0; st < 3; ++st) {
+    PersistLaunch& L = P.p3[st];
+    L.threads = 256;
+    std::vector<WorkItem> v;
+    for (int i = 0; i < (int)d.size(); ++i) {
+      if (!d[i].B) continue;
+      const int nb = st == 1 ? z3_blocks(d[i].Py, d[i].M) : y3_blocks(d[i].nz, d[i].M);
+      for (int blk = 0; blk < nb; ++blk) v.push_back({i, blk});
+      const int len = st == 1 ? d[i].Pz : d[i].Py;
+      L.lds = std::max(L.lds, w3_block_lds(sp, len));
+      L.lds_ref = std::max(L.lds_ref, w3_block_lds(false, len));
+    }
+    if (v.empty()) continue;
+    xcd_order(v);
+    L.off = (int)all.size();
+    L.n = (int)v.size();
+    all.insert(all.end(), v.begin(), v.end());
+    L.grid = w3_persistent_grid(sp, st - 1, L.lds);
+    if (refine) L.grid_ref = w3_persistent_grid(false, st - 1, L.lds_ref);
   }
   if (hipMalloc((void**)&P.descs, d.size() * sizeof(BatchDesc)) != hipSuccess ||
       (refine && hipMalloc((void**)&P.descs_ref, d.size() * sizeof(BatchDesc)) != hipSuccess) ||
@@ -917,6 +952,10 @@ void for_groups(mm_ctx* c, int n, F fn) {
   }
 }
 
+// Launches between the x passes: one per yz layer-count class, and one
+// chain of the three 3-D stages when the batch holds 3-D samples.
+int n_mid(const BatchPlan& P) { return (int)P.pyz.size() + (P.p3[0].n > 0 ? 1 : 0); }
+
 // Reference pass of every batched sample (double precision, same blocks).
 void enqueue_batched_reference(mm_ctx* c, const BatchPlan& P) {
   if (!P.descs_ref) return;
@@ -924,7 +963,13 @@ void enqueue_batched_reference(mm_ctx* c, const BatchPlan& P) {
   if (c->persistent) {
     for (int inv = 0; inv < 2; ++inv) {
       if (inv)
-        for_groups(c, (int)P.pyz.size(), [&](int i, hipStream_t st) {
+        for_groups(c, n_mid(P), [&](int i, hipStream_t st) {
+          if (i == (int)P.pyz.size()) {
+            for (int q = 0; q < 3; ++q)
+              launch_3d_persistent<double>(st, q - 1, P.descs_ref, P.items + P.p3[q].off,
+                                           P.p3[q].n, P.p3[q].lds_ref, P.p3[q].grid_ref);
+            return;
+          }
           const PersistLaunch& L = P.pyz[i];
           launch_yz_persistent<double>(st, P.descs_ref, P.items + L.off, L.n, L.nz, L.lds_ref,
                                        L.grid_ref);
@@ -973,7 +1018,15 @@ void enqueue_batched_iteration(mm_ctx* c, const BatchPlan& P) {
     }
     {
       Timer t(c, KID_YZ);
-      for_groups(c, (int)P.pyz.size(), [&](int i, hipStream_t s) {
+      for_groups(c, n_mid(P), [&](int i, hipStream_t s) {
+        if (i == (int)P.pyz.size()) {
+          for (int q = 0; q < 3; ++q) {
+            const PersistLaunch& L = P.p3[q];
+            if (sp) launch_3d_persistent<float>(s, q - 1, P.descs, P.items + L.off, L.n, L.lds, L.grid);
+            else launch_3d_persistent<double>(s, q - 1, P.descs, P.items + L.off, L.n, L.lds, L.grid);
+          }
+          return;
+        }
         const PersistLaunch& L = P.pyz[i];
         if (sp)
           launch_yz_persistent<float>(s, P.descs, P.items + L.off, L.n, L.nz, L.lds, L.grid);

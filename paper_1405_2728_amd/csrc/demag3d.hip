@@ -31,16 +31,18 @@ namespace mmk {
 constexpr int kY3Waves = 4;   // (kx, z) planes per block of the y passes
 constexpr int kZ3Waves = 4;   // (kx, ky) pencils per block of the z pass
 
+// Logical block L of the forward y pass (planes (kx, z) .. z + 3).
 template <typename T, int VL, bool HALF>
-__global__ void __launch_bounds__(64 * kY3Waves)
-k_y3_fwd(const cx<T>* __restrict__ A, cx<T>* __restrict__ B, int nz, int ny, int nzb,
-         const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+__device__ __forceinline__ void y3_fwd_body(const cx<T>* __restrict__ A, cx<T>* __restrict__ B,
+                                            int nz, int ny, int nzb,
+                                            const cx<T>* __restrict__ twy,
+                                            const int* __restrict__ done, int L) {
   if (done != nullptr && *done != 0) return;
   constexpr int n = 64 * VL;
   constexpr int NG = 8 * VL;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = thread_index();
+  const int lane = tid & 63, w = tid >> 6;
   const int kx = L / nzb;
   const int z = (L - kx * nzb) * kY3Waves + w;
   if (z >= nz) return;                       // no block barrier below
@@ -79,14 +81,23 @@ k_y3_fwd(const cx<T>* __restrict__ A, cx<T>* __restrict__ B, int nz, int ny, int
 
 template <typename T, int VL, bool HALF>
 __global__ void __launch_bounds__(64 * kY3Waves)
-k_y3_inv(cx<T>* __restrict__ A, const cx<T>* __restrict__ B, int nz, int ny, int nzb, int M,
+k_y3_fwd(const cx<T>* __restrict__ A, cx<T>* __restrict__ B, int nz, int ny, int nzb,
          const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+  y3_fwd_body<T, VL, HALF>(A, B, nz, ny, nzb, twy, done, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Logical block L of the inverse y pass.
+template <typename T, int VL, bool HALF>
+__device__ __forceinline__ void y3_inv_body(cx<T>* __restrict__ A, const cx<T>* __restrict__ B,
+                                            int nz, int ny, int nzb, int M,
+                                            const cx<T>* __restrict__ twy,
+                                            const int* __restrict__ done, int L) {
   if (done != nullptr && *done != 0) return;
   constexpr int n = 64 * VL;
   constexpr int NG = 8 * VL;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = thread_index();
+  const int lane = tid & 63, w = tid >> 6;
   const int kx = L / nzb;
   const int z = (L - kx * nzb) * kY3Waves + w;
   if (z >= nz) return;
@@ -118,15 +129,24 @@ k_y3_inv(cx<T>* __restrict__ A, const cx<T>* __restrict__ B, int nz, int ny, int
 }
 
 template <typename T, int VL, bool HALF>
-__global__ void __launch_bounds__(64 * kZ3Waves)
-k_z3(cx<T>* __restrict__ B, int nz, int Py, const T* __restrict__ T3, int rstride, T scale,
-     const cx<T>* __restrict__ twz, const int* __restrict__ done) {
+__global__ void __launch_bounds__(64 * kY3Waves)
+k_y3_inv(cx<T>* __restrict__ A, const cx<T>* __restrict__ B, int nz, int ny, int nzb, int M,
+         const cx<T>* __restrict__ twy, const int* __restrict__ done) {
+  y3_inv_body<T, VL, HALF>(A, B, nz, ny, nzb, M, twy, done, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Logical block L of the z pass with the tensor product (pencils 4 L .. 4 L + 3).
+template <typename T, int VL, bool HALF>
+__device__ __forceinline__ void z3_body(cx<T>* __restrict__ B, int nz, int Py,
+                                        const T* __restrict__ T3, int rstride, T scale,
+                                        const cx<T>* __restrict__ twz,
+                                        const int* __restrict__ done, int L) {
   if (done != nullptr && *done != 0) return;
   constexpr int n = 64 * VL;
   constexpr int NG = 8 * VL;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = thread_index();
+  const int lane = tid & 63, w = tid >> 6;
   const int pen = L * kZ3Waves + w;           // pencil index kx * Py + ky
   const int kx = pen / Py;
   const int ky = pen - kx * Py;
@@ -184,6 +204,51 @@ k_z3(cx<T>* __restrict__ B, int nz, int Py, const T* __restrict__ T3, int rstrid
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+template <typename T, int VL, bool HALF>
+__global__ void __launch_bounds__(64 * kZ3Waves)
+k_z3(cx<T>* __restrict__ B, int nz, int Py, const T* __restrict__ T3, int rstride, T scale,
+     const cx<T>* __restrict__ twz, const int* __restrict__ done) {
+  z3_body<T, VL, HALF>(B, nz, Py, T3, rstride, scale, twz, done,
+                       xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---- persistent batched 3-D stages -----------------------------------------------
+// One launch per stage covers the blocks of every 3-D sample of the batch,
+// whatever its padded lengths (64, 128, 256 or 512): static shares of an
+// XCD-ordered table (persist_loop), a branch on the item's length.
+static_assert(kY3Waves == kZ3Waves, "the 3-D stages share one block size");
+
+template <typename T, int VL>
+__device__ __forceinline__ void w3_item(int stage, const BatchDesc& d, int L) {
+  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  const int nzb = (d.nz + kY3Waves - 1) / kY3Waves;
+  if (stage < 0)
+    y3_fwd_body<T, VL, HALF>((const cx<T>*)d.spec, (cx<T>*)d.B, d.nz, d.ny, nzb,
+                             (const cx<T>*)d.twy, &d.st->done, L);
+  else if (stage > 0)
+    y3_inv_body<T, VL, HALF>((cx<T>*)d.spec, (const cx<T>*)d.B, d.nz, d.ny, nzb, d.M,
+                             (const cx<T>*)d.twy, &d.st->done, L);
+  else
+    z3_body<T, VL, HALF>((cx<T>*)d.B, d.nz, d.Py, (const T*)d.Tt, d.tstride, (T)d.scale,
+                         (const cx<T>*)d.twz, &d.st->done, L);
+}
+
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(64 * kY3Waves)
+k_w3_p(const BatchDesc* __restrict__ descs, const WorkItem* __restrict__ items, int n_items) {
+  persist_loop(n_items, [&](int v) {
+    const WorkItem it = items[v];
+    const BatchDesc& d = descs[it.sample];
+    switch ((STAGE == 0 ? d.Pz : d.Py) >> 6) {
+      case 1: w3_item<T, 1>(STAGE, d, it.block); break;
+      case 2: w3_item<T, 2>(STAGE, d, it.block); break;
+      case 4: w3_item<T, 4>(STAGE, d, it.block); break;
+      case 8: w3_item<T, 8>(STAGE, d, it.block); break;
+      default: break;
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -249,6 +314,59 @@ void launch_z3(hipStream_t s, void* B, int nz, int Py, int Pz, int M, const T* T
   }
 }
 
+int y3_blocks(int nz, int M) { return (M + 1) * ((nz + kY3Waves - 1) / kY3Waves); }
+int z3_blocks(int Py, int M) { return (M + 1) * (Py / kZ3Waves); }
+
+template <typename T, int VL>
+static size_t w3_lds() {
+  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  return (size_t)kY3Waves * wfft_buf<VL, HALF>() * sizeof(cx<T>);
+}
+
+size_t w3_block_lds(bool single, int P) {
+  switch (P) {
+    case 64: return single ? w3_lds<float, 1>() : w3_lds<double, 1>();
+    case 128: return single ? w3_lds<float, 2>() : w3_lds<double, 2>();
+    case 256: return single ? w3_lds<float, 4>() : w3_lds<double, 4>();
+    default: return single ? w3_lds<float, 8>() : w3_lds<double, 8>();
+  }
+}
+
+template <typename T>
+static const void* w3_kernel(int stage) {
+  return stage < 0 ? (const void*)k_w3_p<T, -1>
+                   : (stage > 0 ? (const void*)k_w3_p<T, 1> : (const void*)k_w3_p<T, 0>);
+}
+
+int w3_persistent_grid(bool single, int stage, size_t lds) {
+  const void* k = single ? w3_kernel<float>(stage) : w3_kernel<double>(stage);
+  if (lds > 48 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * kY3Waves, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 8;
+  }
+  const int g = per_cu * cus / 8 * 8;
+  return g < 8 ? 8 : g;
+}
+
+template <typename T>
+void launch_3d_persistent(hipStream_t s, int stage, const BatchDesc* descs, const WorkItem* items,
+                          int n_items, size_t lds, int grid) {
+  const int g = n_items < grid ? n_items : grid;
+  if (g <= 0) return;
+  const void* k = w3_kernel<T>(stage);
+  if (lds > 48 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  void* args[] = {(void*)&descs, (void*)&items, (void*)&n_items};
+  (void)hipLaunchKernel(k, dim3(g), dim3(64 * kY3Waves), args, lds, s);
+}
+
+template void launch_3d_persistent<double>(hipStream_t, int, const BatchDesc*, const WorkItem*, int,
+                                           size_t, int);
+template void launch_3d_persistent<float>(hipStream_t, int, const BatchDesc*, const WorkItem*, int,
+                                          size_t, int);
 template void launch_y3<double>(hipStream_t, void*, void*, int, int, int, int, int, const void*,
                                 const int*);
 template void launch_y3<float>(hipStream_t, void*, void*, int, int, int, int, int, const void*,

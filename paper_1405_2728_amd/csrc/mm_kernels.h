@@ -86,9 +86,12 @@ struct BatchDesc {
   void* g;               // g and s: values of the transform type T
   void* s;
   void* spec;            // spectrum A[kx][z][y][c] (T complex)
-  const void* Tt;        // thin-film tensor (T)
+  const void* Tt;        // thin-film tensor, or the 3-D tensor octant (T)
   const void* twx;       // twiddles, length Px (T complex)
   const void* twy;       // twiddles, length Py (T complex)
+  void* B;               // 3-D path: y-transformed spectrum B[kx][ky][z][c] (else NULL)
+  const void* twz;       // 3-D path: twiddles, length Pz (T complex)
+  int Pz;                // 3-D path: padded z length (else 1)
   MinState* st;
   double* partials;      // [nb3][kNPartial]
   const double* ku_map;  // NULL: scalar ku
@@ -96,7 +99,7 @@ struct BatchDesc {
   double cx, cy, cz;     // 2A/(mu0 Ms D^2)
   double ku, kan;        // scalar Ku; 2/(mu0 Ms)
   double u[3];
-  double scale;          // -Ms/(M Py)
+  double scale;          // -Ms/(M Py), on the 3-D path -Ms/(M Py Pz)
   double Ms, V;
   // defect correction of the single-precision form: pass 0 plain; pass 1
   // transforms m - mref and adds hdref to the demag field; pass 2 (the
@@ -189,6 +192,16 @@ size_t x_block_lds(bool single, int M, int R);
 template <typename T>
 void launch_x_persistent(hipStream_t s, bool inverse, const BatchDesc* descs,
                          const WorkItem* items, int n_items, int threads, size_t lds, int grid);
+// 3-D path (demag3d.hip), persistent batched: stage -1 forward y, 0 z with
+// the tensor product, +1 inverse y; items = (sample, block of the stage's
+// per-sample grid: (M+1) ceil(nz/4) for y, (M+1) Py/4 for z)
+int w3_persistent_grid(bool single, int stage, size_t lds);
+size_t w3_block_lds(bool single, int P);
+int y3_blocks(int nz, int M);
+int z3_blocks(int Py, int M);
+template <typename T>
+void launch_3d_persistent(hipStream_t s, int stage, const BatchDesc* descs, const WorkItem* items,
+                          int n_items, size_t lds, int grid);
 int yz_persistent_grid(bool single, int nz, size_t lds);
 size_t yz_block_lds(bool single, int Py, int nz, int tstride);
 template <typename T>

@@ -37,10 +37,12 @@ def say(*a):
 
 
 # thin wave-eligible shapes of several groups (some with mixed-radix lengths),
-# one Stockham-path shape and one 3-D shape (those two run per sample inside
-# the same sweep)
+# one Stockham-path shape and one 3-D shape on the Stockham x pass (those two
+# run per sample inside the same sweep), one 3-D shape on the wave x pass
+# (batched: the persistent 3-D stages; per sample with the grouped launches)
 SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (20, 10, 1),
-          (10, 8, 6), (260, 130, 1)]   # the last: 640-point x and 320-point y transforms
+          (10, 8, 6), (260, 130, 1),   # 640-point x and 320-point y transforms
+          (48, 20, 5)]
 
 
 def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent=True,
