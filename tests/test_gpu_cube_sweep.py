@@ -9,9 +9,10 @@ effective field (torque < 2 tol: cross-stationarity) and lies within 1e-3 of
 the FP64 state (|dm|_inf: the two land in the same basin over these fields;
 measured <= 1e-4); the oracle's own torque at the FP64 states of the first
 and last field is below tol (its FFT convolution at 256^3).  Beyond 60 mT a
-switching event sends the two forms into mirror-image metastable states (the
-energy is symmetric under y -> -y with the field in the x-z plane); bench.py
---workload cube-sweep reports the whole 0..200 mT sweep.
+switching event can send the two forms into mirror-image metastable states
+(the energy is symmetric under y -> -y with the field in the x-z plane;
+which one a run reaches follows its rounding path), so the test stops
+there; bench.py --workload cube-sweep reports the whole 0..200 mT sweep.
 """
 
 import sys
