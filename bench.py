@@ -100,6 +100,7 @@ def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False):
     ctx.set_option("autotune", 1)
     ctx.set_geometry(0, nx, ny, nz, *w["d"])
     rows = ctx.rows_per_block(0)
+    yz_var = ctx.yz_variant(0)
     ctx.set_material(0, w["Ms"], w["A"], w["Ku"], w["u"])
     ctx.set_field(0, w["fields"][field])
     m = torch.tensor(w["m0"], dtype=torch.float64, device="cuda")
@@ -120,7 +121,7 @@ def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False):
     kb = ctx.kernel_bytes(0)
     ctx.close()
     return {"iters": r["iters"], "evals": r["heff_evals"], "seconds": dt, "prof": prof,
-            "bytes": kb, "torque": r["torque"], "rows_per_block": rows}
+            "bytes": kb, "torque": r["torque"], "rows_per_block": rows, "yz_variant": yz_var}
 
 
 def stored_traffic(prec, kernel, workload):
@@ -466,7 +467,8 @@ def main():
         "dtype": "f64" if a.prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wdesc, "precision": a.prec, "padded_grid": padded},
-        "tile": {"rows_per_block": main_run["rows_per_block"], "chosen_by": "autotuner"},
+        "tile": {"rows_per_block": main_run["rows_per_block"],
+                 "yz_variant": main_run["yz_variant"], "chosen_by": "autotuner"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0,
                      "unit": "GB/s", "frac": achieved / 8000.0,
                      "traffic": traffic, "avg_kernel_us": avg_s * 1e6,

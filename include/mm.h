@@ -284,24 +284,35 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * single-precision thin-film block does not fit in double precision run
  * without it); mm_heff, mm_field_terms, mm_energy and the derivative calls
  * always use the plain single-precision convolution), "autotune" (1: the
- * tile autotuner of the batched form's passes.  mm_set_geometry times the
- * fused x passes (xf + xil) for every valid number of rows per block on
- * the sample's own buffers and keeps the fastest; choices are cached per
- * precision, grid and demag path for the life of the process; default 0
- * uses a fixed heuristic, so that results do not depend on timing),
+ * tile autotuner.  mm_set_geometry times the fused x passes (xf + xil) for
+ * every valid number of rows per block on the sample's own buffers and
+ * keeps the fastest, then, on the thin-film path, the yz pass's two
+ * occupancy variants where the grid has two (the wave kernel compiled for
+ * 3 or 2 resident waves per SIMD in double precision, 6 or 4 in single,
+ * where a block's 3 nz waves fit); choices are cached per precision, grid
+ * and demag path for the life of the process; default 0 uses a fixed
+ * heuristic and the first variant, so that results do not depend on
+ * timing; the variants compute the same bits),
  * "rows_per_block" (0 = automatic; otherwise that tile for every later
  * mm_set_geometry, which fails with MM_EINVAL where it is not valid: for
- * testing every tile), "mixed_radix" (default 1, read by mm_set_geometry:
+ * testing every tile), "yz_variant" (-1 = automatic; 0 or 1 that yz
+ * occupancy variant for every later mm_set_geometry, which fails with
+ * MM_EINVAL where the grid has no such variant: for testing), "mixed_radix" (default 1, read by mm_set_geometry:
  * the padded x length is the smaller of the power of two >= 2 nx - 1 and
  * the multiple of 128 >= 2 nx - 1 (up to 1024), the thin-film y length the
  * smaller of the power of two >= 2 ny - 1 and the multiple of 64 (up to
  * 512), so that transforms of 64 VL points with VL = 3, 5, 6, 7 take the
  * place of the next power of two; 0 keeps powers of two),
- * "concurrent_groups" (default 1: in batched sweeps the launch groups of a
+ * "concurrent_groups" (default 1: in batched sweeps the launches of a
  * pass, which touch disjoint samples, run on four auxiliary streams of
  * default priority forked from and joined back into the context's stream,
  * as parallel branches of the captured graph; 0 launches them one after
- * another; results are the same either way).  Unknown keys or values give
+ * another; results are the same either way), "persistent" (default 1: in
+ * batched sweeps each pass is one persistent launch covering every
+ * transform length (the x passes one per rows-per-block class, the thin yz
+ * pass one per layer count, the full 3-D path's three stages one each);
+ * 0: one launch per group of equal lengths, and full 3-D samples run one
+ * by one; results are the same either way).  Unknown keys or values give
  * MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 
@@ -309,6 +320,10 @@ int mm_set_option(mm_ctx* ctx, const char* key, double value);
  * heuristic, the autotuner or the rows_per_block option chose it at
  * mm_set_geometry. */
 int mm_rows_per_block(mm_ctx* ctx, int sample, int* rows);
+
+/* Occupancy variant of the sample's thin-film yz pass (host int output: 0
+ * or 1), as the autotuner chose it at mm_set_geometry (0 without it). */
+int mm_yz_variant(mm_ctx* ctx, int sample, int* var);
 
 /* Counters of one sample since its last mm_set_geometry: total
  * effective-field evaluations and updates (host int64_t outputs). */

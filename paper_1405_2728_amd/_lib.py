@@ -58,6 +58,7 @@ SIGNATURES = {
     "mm_last_step": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(StepInfo)]),
     "mm_counters": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mm_rows_per_block": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "mm_yz_variant": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "mm_supported": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "mm_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "mm_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),

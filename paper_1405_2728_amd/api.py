@@ -260,6 +260,11 @@ class Context:
         self._check(self._lib.mm_rows_per_block(self._h, sample, C.byref(r)))
         return r.value
 
+    def yz_variant(self, sample):
+        r = C.c_int()
+        self._check(self._lib.mm_yz_variant(self._h, sample, C.byref(r)))
+        return r.value
+
     # -- timing ---------------------------------------------------------------
     def profile(self, kernels=None):
         """Time the named kernels (None or [] stops; "all" times every

@@ -43,6 +43,7 @@ struct Sample {
   double dx = 0, dy = 0, dz = 0, V = 0;
   int path = PATH_NONE;
   int Px = 0, Py = 0, Pz = 1, M = 0, R3 = 1, nb3 = 0, tstride = 0;
+  int yz_var = 0;             // occupancy variant of the thin yz wave kernel (tile tuner)
   double Ms = 0, A = 0, Ku = 0, u[3] = {1, 0, 0}, H[3] = {0, 0, 0};
   double* ku_map = nullptr;
   void* Tt = nullptr;
@@ -125,6 +126,7 @@ struct mm_ctx {
   int refine = 1;               // single-precision form: defect correction on
   int autotune = 0;             // 1: time the x-pass tiles at mm_set_geometry
   int rows_forced = 0;          // > 0: rows per block of the x passes (tests)
+  int yz_forced = -1;           // >= 0: occupancy variant of the thin yz pass (tests)
   int mixed_radix = 1;          // 1: wave lengths 64 VL (VL = 3, 5, 6, 7) where shorter
   int concurrent_groups = 1;    // batched passes: launch groups on forked streams
   int persistent = 1;           // batched passes: one persistent launch per pass (per
@@ -518,14 +520,15 @@ struct Conv {
   void* twz;
   void* B;
   int tstride, R;
+  int yz_var;
 };
 
 Conv conv_main(const mm_ctx* c, const Sample& s) {
-  return {single(c), s.Tt, s.spec, s.twx, s.twy, s.twz, s.B, s.tstride, s.R3};
+  return {single(c), s.Tt, s.spec, s.twx, s.twy, s.twz, s.B, s.tstride, s.R3, s.yz_var};
 }
 
 Conv conv_ref(const Sample& s) {
-  return {false, s.rTt, s.rspec, s.rtwx, s.rtwy, s.rtwz, s.rB, s.rtstride, s.rR3};
+  return {false, s.rTt, s.rspec, s.rtwx, s.rtwy, s.rtwz, s.rB, s.rtstride, s.rR3, 0};
 }
 
 bool use_ref(const mm_ctx* c, const Sample& s) { return single(c) && c->refine && s.has_ref; }
@@ -570,10 +573,10 @@ void enqueue_demag_mid(mm_ctx* c, const Sample& s, const Conv& v, const int* don
     const double scale = -s.Ms / ((double)s.M * (double)s.Py);
     if (v.sp)
       launch_yz_thin<float>(st, v.spec, s.nz, s.ny, s.Py, s.M, (const float*)v.Tt, v.tstride,
-                            (float)scale, v.twy, done);
+                            (float)scale, v.twy, done, v.yz_var);
     else
       launch_yz_thin<double>(st, v.spec, s.nz, s.ny, s.Py, s.M, (const double*)v.Tt, v.tstride,
-                             scale, v.twy, done);
+                             scale, v.twy, done, v.yz_var);
   }
   c->prof = prof;
 }
@@ -1206,6 +1209,78 @@ int choose_rows(mm_ctx* c, Sample& s) {
   return MM_OK;
 }
 
+std::map<TuneKey, int>& yz_tune_cache() {
+  static std::map<TuneKey, int> m;
+  return m;
+}
+
+// Mean time of one thin yz pass with occupancy variant var (microseconds)
+// on the sample's tensor and spectrum buffer (scratch contents: every
+// iteration's forward x pass rewrites the spectrum).
+int time_yz(mm_ctx* c, Sample& s, int var, double* us) {
+  hipStream_t st = c->stream;
+  const bool sp = single(c);
+  auto pass = [&]() {
+    if (sp)
+      launch_yz_thin<float>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const float*)s.Tt, s.tstride,
+                            -1.0f, s.twy, nullptr, var);
+    else
+      launch_yz_thin<double>(st, s.spec, s.nz, s.ny, s.Py, s.M, (const double*)s.Tt, s.tstride,
+                             -1.0, s.twy, nullptr, var);
+  };
+  constexpr int kReps = 5;
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  pass();
+  pass();
+  hipError_t e = hipEventRecord(e0, st);
+  for (int q = 0; q < kReps && e == hipSuccess; ++q) pass();
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  c->ev_pool.push_back(e0);
+  c->ev_pool.push_back(e1);
+  if (e != hipSuccess) return fail(c, MM_EHIP, std::string("yz timing: ") + hipGetErrorString(e));
+  *us = 1e3 * ms / kReps;
+  return MM_OK;
+}
+
+// The thin yz pass's occupancy variant: with the autotune option, both
+// variants (where the grid has two) are timed in three interleaved rounds
+// and the faster kept, cached per precision, grid and padded lengths.
+int choose_yz(mm_ctx* c, Sample& s) {
+  const bool sp = single(c);
+  s.yz_var = 0;
+  const int nvar = s.path == PATH_THIN ? yz_variants(sp, s.nz, s.Py) : 1;
+  if (c->yz_forced >= 0) {
+    if (c->yz_forced >= nvar)
+      return fail(c, MM_EINVAL, "yz_variant: this grid's yz pass has no such variant");
+    s.yz_var = c->yz_forced;
+    return MM_OK;
+  }
+  if (!c->autotune || nvar < 2) return MM_OK;
+  const TuneKey key{sp ? 1 : 0, s.nx, s.ny, s.nz, s.path, s.Px, s.Py};
+  std::lock_guard<std::mutex> lock(tune_mutex());
+  auto it = yz_tune_cache().find(key);
+  if (it != yz_tune_cache().end()) {
+    s.yz_var = it->second;
+    return MM_OK;
+  }
+  double best[2] = {0.0, 0.0};
+  for (int round = 0; round < 3; ++round) {
+    for (int v = 0; v < 2; ++v) {
+      double us = 0.0;
+      const int rc = time_yz(c, s, v, &us);
+      if (rc != MM_OK) return rc;
+      if (round == 0 || us < best[v]) best[v] = us;
+    }
+  }
+  s.yz_var = best[1] < best[0] ? 1 : 0;
+  yz_tune_cache()[key] = s.yz_var;
+  return MM_OK;
+}
+
 int status_of(int done) {
   switch (done) {
     case 1: return MM_OK;
@@ -1541,6 +1616,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   if (full) launch_twiddles(c->stream, s.twz, s.Pz, sp);
   int rc = full ? build_tensor3d(c, s) : build_tensor(c, s);
   if (rc == MM_OK) rc = choose_rows(c, s);
+  if (rc == MM_OK) rc = choose_yz(c, s);
   if (rc != MM_OK) {
     free_sample(s);
     return rc;
@@ -1959,6 +2035,10 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->persistent = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
+  } else if (!std::strcmp(key, "yz_variant")) {
+    if (value != -1 && value != 0 && value != 1)
+      return fail(c, MM_EINVAL, "yz_variant is -1 (automatic), 0 or 1");
+    c->yz_forced = (int)value;
   } else if (!std::strcmp(key, "rows_per_block")) {
     if (value < 0 || value > 64 || value != std::floor(value))
       return fail(c, MM_EINVAL, "rows_per_block is 0 (automatic) or a tile size");
@@ -1977,6 +2057,14 @@ int mm_rows_per_block(mm_ctx* c, int sample, int* rows) {
   if (rc != MM_OK) return rc;
   if (!rows) return fail(c, MM_EINVAL, "null pointer");
   *rows = c->smp[sample].R3;
+  return MM_OK;
+}
+
+int mm_yz_variant(mm_ctx* c, int sample, int* var) {
+  int rc = check_sample(c, sample, false);
+  if (rc != MM_OK) return rc;
+  if (!var) return fail(c, MM_EINVAL, "null pointer");
+  *var = c->smp[sample].yz_var;
   return MM_OK;
 }
 

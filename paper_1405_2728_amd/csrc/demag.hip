@@ -427,12 +427,18 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
 }
 
 // waves per SIMD the yz kernels are compiled for: double precision holds
-// one 4-layer block per CU (LDS), single precision two
+// one 4-layer block per CU (LDS), single precision two.  The tile tuner may
+// pick the alternative bound yz_alt_waves_per_eu (fewer resident waves, more
+// registers per wave) where a block's 3 nz waves still fit it.
 template <typename T>
 __host__ __device__ constexpr int yz_waves_per_eu() { return sizeof(T) == 8 ? 3 : 6; }
+template <typename T>
+__host__ __device__ constexpr int yz_alt_waves_per_eu() { return sizeof(T) == 8 ? 2 : 4; }
+template <typename T, int NZ>
+__host__ __device__ constexpr bool yz_has_alt() { return 4 * yz_alt_waves_per_eu<T>() >= 3 * NZ; }
 
-template <typename T, int VL, int NZ>
-__global__ void __launch_bounds__(192 * NZ, yz_waves_per_eu<T>())
+template <typename T, int VL, int NZ, int WPE>
+__global__ void __launch_bounds__(192 * NZ, WPE)
 k_yz_wave(cx<T>* __restrict__ A, int ny, int M, const T* __restrict__ Tt, int tstride, T scale,
           const cx<T>* __restrict__ twy, const int* __restrict__ done) {
   yz_wave_body<T, VL, NZ>(A, ny, M, Tt, tstride, scale, twy, done, blockIdx.x);
@@ -592,24 +598,37 @@ static void yz_dispatch(hipStream_t s, void* A, int ny, int Py, int M, const T* 
   }
 }
 
-template <typename T, int VL, int NZ>
-static void yz_wave_dispatch(hipStream_t s, void* A, int ny, int M, const T* Tt, int tstride,
-                             T scale, const void* twy, const int* done) {
+template <typename T, int VL, int NZ, int WPE>
+static void yz_wave_launch(hipStream_t s, void* A, int ny, int M, const T* Tt, int tstride,
+                           T scale, const void* twy, const int* done) {
   const size_t lds = yz_lds_bytes<T, VL, NZ>(tstride);
-  auto k = k_yz_wave<T, VL, NZ>;
+  auto k = k_yz_wave<T, VL, NZ, WPE>;
   set_lds(k, lds);
   hipLaunchKernelGGL(k, dim3(M + 1), dim3(192 * NZ), lds, s, (cx<T>*)A, ny, M, Tt, tstride, scale,
                      (const cx<T>*)twy, done);
 }
 
+template <typename T, int VL, int NZ>
+static void yz_wave_dispatch(hipStream_t s, void* A, int ny, int M, const T* Tt, int tstride,
+                             T scale, const void* twy, const int* done, int var) {
+  if constexpr (yz_has_alt<T, NZ>()) {
+    if (var == 1) {
+      yz_wave_launch<T, VL, NZ, yz_alt_waves_per_eu<T>()>(s, A, ny, M, Tt, tstride, scale, twy,
+                                                          done);
+      return;
+    }
+  }
+  yz_wave_launch<T, VL, NZ, yz_waves_per_eu<T>()>(s, A, ny, M, Tt, tstride, scale, twy, done);
+}
+
 template <typename T, int VL>
 static void yz_wave_nz(hipStream_t s, void* A, int nz, int ny, int M, const T* Tt, int tstride,
-                       T scale, const void* twy, const int* done) {
+                       T scale, const void* twy, const int* done, int var) {
   switch (nz) {
-    case 1: yz_wave_dispatch<T, VL, 1>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
-    case 2: yz_wave_dispatch<T, VL, 2>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
-    case 3: yz_wave_dispatch<T, VL, 3>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
-    default: yz_wave_dispatch<T, VL, 4>(s, A, ny, M, Tt, tstride, scale, twy, done); break;
+    case 1: yz_wave_dispatch<T, VL, 1>(s, A, ny, M, Tt, tstride, scale, twy, done, var); break;
+    case 2: yz_wave_dispatch<T, VL, 2>(s, A, ny, M, Tt, tstride, scale, twy, done, var); break;
+    case 3: yz_wave_dispatch<T, VL, 3>(s, A, ny, M, Tt, tstride, scale, twy, done, var); break;
+    default: yz_wave_dispatch<T, VL, 4>(s, A, ny, M, Tt, tstride, scale, twy, done, var); break;
   }
 }
 
@@ -617,19 +636,25 @@ bool yz_wave_ok(int nz, int Py) {
   return nz >= 1 && nz <= 4 && Py % 64 == 0 && Py >= 64 && Py <= 512;
 }
 
+int yz_variants(bool single, int nz, int Py) {
+  if (!yz_wave_ok(nz, Py)) return 1;
+  const int alt = single ? yz_alt_waves_per_eu<float>() : yz_alt_waves_per_eu<double>();
+  return 4 * alt >= 3 * nz ? 2 : 1;
+}
+
 template <typename T>
 void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt,
-                    int tstride, T scale, const void* twy, const int* done) {
+                    int tstride, T scale, const void* twy, const int* done, int var) {
   if (yz_wave_ok(nz, Py)) {
     switch (Py) {
-      case 64: yz_wave_nz<T, 1>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      case 128: yz_wave_nz<T, 2>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      case 192: yz_wave_nz<T, 3>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      case 256: yz_wave_nz<T, 4>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      case 320: yz_wave_nz<T, 5>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      case 384: yz_wave_nz<T, 6>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      case 448: yz_wave_nz<T, 7>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
-      default: yz_wave_nz<T, 8>(s, A, nz, ny, M, Tt, tstride, scale, twy, done); return;
+      case 64: yz_wave_nz<T, 1>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      case 128: yz_wave_nz<T, 2>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      case 192: yz_wave_nz<T, 3>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      case 256: yz_wave_nz<T, 4>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      case 320: yz_wave_nz<T, 5>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      case 384: yz_wave_nz<T, 6>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      case 448: yz_wave_nz<T, 7>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
+      default: yz_wave_nz<T, 8>(s, A, nz, ny, M, Tt, tstride, scale, twy, done, var); return;
     }
   }
   switch (nz) {
@@ -742,8 +767,8 @@ template void launch_inv_x<float>(hipStream_t, const void*, int, int, int, int, 
                                   const void*, const int*);
 template void launch_fft_cols<double>(hipStream_t, void*, int, int, const void*);
 template void launch_yz_thin<double>(hipStream_t, void*, int, int, int, int, const double*, int,
-                                     double, const void*, const int*);
+                                     double, const void*, const int*, int);
 template void launch_yz_thin<float>(hipStream_t, void*, int, int, int, int, const float*, int, float,
-                                    const void*, const int*);
+                                    const void*, const int*, int);
 
 }  // namespace mmk

@@ -164,9 +164,12 @@ void launch_inv_x(hipStream_t s, const void* in, int rows, int ncomp, int nx_out
                   int rows_per_block, double* out, const void* twx, const int* done);
 template <typename T>
 void launch_fft_cols(hipStream_t s, void* data, int n, int nseq, const void* tw);
+// var: the wave kernel's occupancy variant (0 default; 1 the alternative
+// bound, where yz_variants gives 2), chosen by the tile tuner
 template <typename T>
 void launch_yz_thin(hipStream_t s, void* A, int nz, int ny, int Py, int M, const T* Tt,
-                    int tstride, T scale, const void* twy, const int* done);
+                    int tstride, T scale, const void* twy, const int* done, int var = 0);
+int yz_variants(bool single, int nz, int Py);
 // elements per kx slab of the thin tensor (padded to 16 bytes)
 inline int thin_tensor_stride(int nz, int Py, bool single) {
   const int e = nz * (Py / 2 + 1) * 6;

@@ -563,6 +563,50 @@ def test_row_tiles_agree(torch_cuda, prec, shape):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", [(100, 40, 2), (64, 32, 1), (400, 200, 4)])
+def test_yz_variants_agree(torch_cuda, prec, shape):
+    """The thin yz pass's occupancy variants (the autotuner's yz search
+    space) run the same code under another register bound: the same field
+    and the same iterates bit for bit.  Double precision has the second
+    variant only for nz <= 2 (a block's 3 nz waves must fit 2 per SIMD)."""
+    from paper_1405_2728_amd import Context, MMError
+    torch = torch_cuda
+    nx, ny, nz = shape
+    d = (5e-9,) * 3
+    say("case yz variants", prec, shape)
+    rng = np.random.default_rng(9)
+    m0 = synth.random_unit(nx, ny, nz, rng)
+    runs = {}
+    for var in (0, 1):
+        ctx = Context(prec)
+        ctx.set_option("yz_variant", var)
+        try:
+            ctx.set_geometry(0, nx, ny, nz, *d)
+        except MMError as e:
+            assert e.code == -1 and var == 1 and prec == "fp64" and nz > 2
+            ctx.close()
+            continue
+        assert ctx.yz_variant(0) == var
+        ctx.set_material(0, 8e5, 1.3e-11, 500.0, (1, 0, 0))
+        ctx.set_field(0, (1e4, 0, 0))
+        m = torch.tensor(m0, device="cuda")
+        H = ctx.heff(0, m).cpu().numpy()
+        ctx.minimize_to_tol(0, m, tol=0.0, max_iter=10)
+        runs[var] = (H, m.cpu().numpy())
+        ctx.close()
+    say("  variants", sorted(runs))
+    if len(runs) == 2:
+        assert np.array_equal(runs[0][0], runs[1][0])
+        assert np.array_equal(runs[0][1], runs[1][1])
+    ctx = Context(prec)
+    ctx.set_option("autotune", 1)
+    ctx.set_geometry(0, nx, ny, nz, *d)
+    say("  autotuned yz variant", ctx.yz_variant(0))
+    assert ctx.yz_variant(0) in runs
+    ctx.close()
+
+
 def test_mixed_without_fp64_reference(torch_cuda):
     """32x300x4: the single-precision thin-film block (3 nz Py = 12288
     values, Py = 1024) fits, the double-precision one does not, so the mixed

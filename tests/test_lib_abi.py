@@ -108,6 +108,11 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"mixed_radix", 1.0) == 0
         assert lib.mm_set_option(h, b"concurrent_groups", 0.0) == 0
         assert lib.mm_set_option(h, b"concurrent_groups", 1.0) == 0
+        assert lib.mm_set_option(h, b"persistent", 0.0) == 0
+        assert lib.mm_set_option(h, b"persistent", 1.0) == 0
+        assert lib.mm_set_option(h, b"yz_variant", 2.0) == -1
+        assert lib.mm_set_option(h, b"yz_variant", 1.0) == 0
+        assert lib.mm_set_option(h, b"yz_variant", -1.0) == 0
         assert lib.mm_set_option(h, b"bb_switch", -0.5) == -1
         assert lib.mm_set_option(h, b"bb_switch", float("inf")) == -1
         assert lib.mm_set_option(h, b"bb_switch", 0.5) == 0
@@ -129,6 +134,7 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"rows_per_block", 0.0) == 0
         r = C.c_int()
         assert lib.mm_rows_per_block(h, 0, C.byref(r)) == -5
+        assert lib.mm_yz_variant(h, 0, C.byref(r)) == -5
     finally:
         lib.mm_destroy(h)
     lib.mm_destroy(None)
