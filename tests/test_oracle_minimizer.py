@@ -307,6 +307,55 @@ def test_sweep_warm_start_repeated_field_costs_nothing():
     assert np.allclose(out["mavg"][0], out["mavg"][1])
 
 
+def test_sweep_records_each_fields_state_and_restarts_bb():
+    """The sweep's per-field records: <m> is the cell mean of that field's
+    final state (summed here with math.fsum per component, not by the
+    sweep's own reduction); every field's run is a fresh BB run from the
+    previous field's state (the step restarts at tau0), so it equals
+    minimize() started there, iterate count and state."""
+    import math
+    P = small_problem()
+    H = np.array([[2e4, 0.0, 0.0], [-1e4, 2e3, 0.0], [-3e4, 0.0, 1e3]])
+    m0 = random_unit((2, 4, 6), 14)
+    out = mz.sweep(P, m0, H, tol=1e-7)
+    assert out["converged"].all()
+    for f in range(len(H)):
+        mf = out["states"][f]
+        for c in range(3):
+            ref = math.fsum(mf[c].ravel().tolist()) / mf[c].size
+            assert abs(out["mavg"][f][c] - ref) < 1e-15
+    prev = m0 / np.linalg.norm(m0, axis=0)
+    for f in range(len(H)):
+        Q = small_problem(H_ext=tuple(H[f]))
+        r = mz.minimize(Q, prev, tol=1e-7, record=True)
+        assert r["taus"][0] == mz.default_tau0(Q.Ms)
+        assert r["iters"] == out["iters"][f]
+        assert np.array_equal(r["m"], out["states"][f])
+        prev = r["m"]
+
+
+@pytest.mark.parametrize("psi_deg", [30.0, 60.0])
+def test_sweep_switches_at_the_stoner_wohlfarth_field(psi_deg):
+    """One cubic cell (isotropic self-demag, no exchange) swept from +1.2 to
+    -1.2 H_K in steps of 0.02 H_K along psi from the easy axis: the sweep's
+    <m> along the easy axis changes sign at the first field beyond the
+    astroid's switching field (closed form), and the branch before it stays
+    on the metastable side."""
+    Ms, K = 8e5, 500.0
+    HK = 2 * K / (MU0 * Ms)
+    psi = np.deg2rad(psi_deg)
+    hsw = sw_switching_field(psi)
+    hs = np.round(np.arange(1.2, -1.2 - 1e-9, -0.02), 10)
+    H = np.stack([hs * HK * np.cos(psi), hs * HK * np.sin(psi), 0.0 * hs], axis=1)
+    P = fields.Problem(1, 1, 1, 5e-9, 5e-9, 5e-9, Ms=Ms, A=0.0, Ku=K, u=(1, 0, 0))
+    m0 = np.array([1.0, 0.0, 0.0]).reshape(3, 1, 1, 1)
+    out = mz.sweep(P, m0, H, tol=1e-10, max_iter=200000)
+    assert out["converged"].all()
+    first = next(f for f in range(len(hs)) if out["mavg"][f][0] < 0)
+    expect = next(f for f in range(len(hs)) if hs[f] < -hsw)
+    assert first == expect, (psi_deg, first, expect, hs[first], -hsw)
+
+
 def test_relaxation_lowers_energy_c0_like():
     P = fields.Problem(16, 8, 1, 5e-9, 5e-9, 5e-9, Ms=8e5, A=1.3e-11, Ku=500.0)
     m0 = random_unit((1, 8, 16), 12)
