@@ -76,13 +76,18 @@ def parse():
     p.add_argument("--quick", action="store_true",
                    help="only the timed run (for profilers): no profiled pass, no other "
                         "precision, no CPU baseline")
+    p.add_argument("--rows-per-block", type=int, default=0, metavar="R",
+                   help="with --quick: x-pass tile R instead of the autotuner's choice (for "
+                        "profiler runs, whose counters distort the tuner's timings)")
+    p.add_argument("--yz-variant", type=int, default=-1, metavar="V",
+                   help="with --quick: yz occupancy variant V instead of the autotuner's choice")
     p.add_argument("--copy-probe", type=float, default=0.0, metavar="MB",
                    help="run a plain device copy of MB megabytes 5 times and exit "
                         "(calibration of the memory-traffic counters)")
     return p.parse_args()
 
 
-def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False):
+def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False, rows=0, yz=-1):
     """Warm up, then time `steps` iterations.  With `profile` ("all" or a
     list of kernel names), the library records HIP events around those
     kernels' launches in the timed region (on the library's stream) and the
@@ -98,6 +103,9 @@ def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False):
     ctx = Context(prec, stream=stream)
     ctx.set_option("use_graph", 1 if graph else 0)
     ctx.set_option("autotune", 1)
+    if rows:
+        ctx.set_option("rows_per_block", rows)
+    ctx.set_option("yz_variant", yz)
     ctx.set_geometry(0, nx, ny, nz, *w["d"])
     rows = ctx.rows_per_block(0)
     yz_var = ctx.yz_variant(0)
@@ -422,11 +430,13 @@ def main():
     w = synth.workload(wid)
     label = "x".join(str(v) for v in w["n"])
     if a.quick:
-        q = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field)
+        q = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field,
+                    rows=a.rows_per_block, yz=a.yz_variant)
         r = {"value": q["iters"] / q["seconds"], "unit": "iters/s", "precision": a.prec,
              "steps": a.steps}
         if a.graph:
-            g = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field, graph=True)
+            g = run_gpu(a.prec, a.steps, a.warmup, w, profile=False, field=field, graph=True,
+                        rows=a.rows_per_block, yz=a.yz_variant)
             r["graph_value"] = g["iters"] / g["seconds"]
         print(json.dumps(r))
         return
