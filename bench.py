@@ -290,6 +290,28 @@ def loops(torch, bb_switch=0.0, line_search=False):
     return out
 
 
+def copy_ceiling(torch, mb=1024, reps=10):
+    """Bandwidth of a plain device copy of `mb` megabytes (read + write bytes
+    over the time, HIP events on torch's stream): the attainable HBM
+    ceiling next to the 8 TB/s peak."""
+    n = int(mb * 1e6 / 8)
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * 8 * n / s / 1e9
+
+
 def host_cores():
     """Threads the CPU baseline may use: the CPUs this process may run on,
     capped by OMP_NUM_THREADS where it is set (the box's share)."""
@@ -457,6 +479,7 @@ def main():
     avg_s = ms / 1e3 / max(n, 1)
     achieved = main_run["bytes"][dom] / avg_s / 1e9
     traffic = stored_traffic(a.prec, dom, a.workload)
+    copy_gbps = copy_ceiling(torch)
     # launches per iteration weight each kernel (the mixed form's reference
     # pass runs once per poll_every iterations)
     per_iter_bytes = sum(main_run["bytes"][k] * v[1] / all_run["iters"]
@@ -482,7 +505,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0,
                      "unit": "GB/s", "frac": achieved / 8000.0,
                      "traffic": traffic, "avg_kernel_us": avg_s * 1e6,
-                     "algorithmic_bytes": main_run["bytes"][dom]},
+                     "algorithmic_bytes": main_run["bytes"][dom],
+                     "traffic_GBps": traffic / avg_s / 1e9 if traffic else None,
+                     "copy_ceiling_GBps": copy_gbps},
         "iteration": {"model_bytes": per_iter_bytes,
                       "model_GBps": per_iter_bytes * ips / 1e9,
                       "model_frac_of_8TBps": per_iter_bytes * ips / 8e12,
