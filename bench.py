@@ -149,7 +149,7 @@ def stored_traffic(prec, kernel, workload):
 
 
 def run_batched(torch, batched, field_step=10, prec="fp64", mixed_radix=1, concurrent=1,
-                persistent=1):
+                persistent=1, rebuild=None):
     """Sweep the 64 platelets through every field_step-th field of their
     loop; returns (summed iterations, seconds, status)."""
     import synth
@@ -163,6 +163,8 @@ def run_batched(torch, batched, field_step=10, prec="fp64", mixed_radix=1, concu
     ctx.set_option("mixed_radix", mixed_radix)
     ctx.set_option("concurrent_groups", concurrent)
     ctx.set_option("persistent", persistent)
+    if rebuild is not None:
+        ctx.set_option("batch_rebuild", rebuild)
     ms, H = [], []
     for k, p in enumerate(plats):
         ctx.set_geometry(k, *p["n"], *p["d"])

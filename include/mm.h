@@ -312,8 +312,11 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * transform length (the x passes one per rows-per-block class, the thin yz
  * pass one per layer count, the full 3-D path's three stages one each);
  * 0: one launch per group of equal lengths, and full 3-D samples run one
- * by one; results are the same either way).  Unknown keys or values give
- * MM_EINVAL. */
+ * by one; results are the same either way), "batch_rebuild" (default 0.75:
+ * in batched sweeps, once the running samples are at most this fraction of
+ * the batch, its work tables are rebuilt from the running ones and the
+ * graph captured again; 0 never; results are the same either way).
+ * Unknown keys or values give MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 
 /* Rows per block of the sample's fused x passes (host int output), as the

@@ -129,6 +129,8 @@ struct mm_ctx {
   int yz_forced = -1;           // >= 0: occupancy variant of the thin yz pass (tests)
   int mixed_radix = 1;          // 1: wave lengths 64 VL (VL = 3, 5, 6, 7) where shorter
   int concurrent_groups = 1;    // batched passes: launch groups on forked streams
+  double batch_rebuild = 0.75;  // batched sweeps: rebuild the tables once the running
+                                // samples are at most this fraction of the plan's (0: never)
   int persistent = 1;           // batched passes: one persistent launch per pass (per
                                 // layer count for yz); 0: one launch per group of
                                 // equal transform lengths
@@ -1949,11 +1951,13 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
         --left;
         if (in_batch[k]) --batch_left;
       }
-    // once a quarter of the batch has finished, the tables are rebuilt from
-    // the samples still running (and the graph captured again), so that the
-    // launches stop walking finished samples' blocks; results do not change,
-    // every sample's blocks and reductions being its own
-    if (batch_left >= 2 && 4 * batch_left <= 3 * (int)plan->members.size()) {
+    // once the running samples are at most the batch_rebuild fraction of the
+    // plan's, the tables are rebuilt from them (and the graph captured
+    // again), so that the launches stop walking finished samples' blocks;
+    // results do not change, every sample's blocks and reductions being its
+    // own
+    if (batch_left >= 2 && c->batch_rebuild > 0.0 &&
+        batch_left <= c->batch_rebuild * (double)plan->members.size()) {
       std::unique_ptr<BatchPlan> np(new BatchPlan);
       const int rc = build_batch(c, m, *np, &running);
       if (rc != MM_OK) {
@@ -2031,6 +2035,10 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->mixed_radix = value != 0.0;
   } else if (!std::strcmp(key, "concurrent_groups")) {
     c->concurrent_groups = value != 0.0;
+  } else if (!std::strcmp(key, "batch_rebuild")) {
+    if (!(value >= 0.0 && value < 1.0))
+      return fail(c, MM_EINVAL, "batch_rebuild is a fraction in [0, 1)");
+    c->batch_rebuild = value;
   } else if (!std::strcmp(key, "persistent")) {
     c->persistent = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
