@@ -46,12 +46,14 @@ SHAPES = [(64, 32, 1), (100, 40, 2), (70, 33, 1), (130, 64, 2), (256, 128, 1), (
 
 
 def run(torch, prec, batched, graph=False, shapes=SHAPES, n_fields=4, concurrent=True,
-        bb_switch=0.0, persistent=True):
+        bb_switch=0.0, persistent=True, rebuild=None):
     from paper_1405_2728_amd import Context
     stream = torch.cuda.Stream() if graph else None
     ctx = Context("mixed" if prec == "mixed_plain" else prec, n_samples=len(shapes), stream=stream)
     ctx.set_option("concurrent_groups", 1 if concurrent else 0)
     ctx.set_option("persistent", 1 if persistent else 0)
+    if rebuild is not None:
+        ctx.set_option("batch_rebuild", rebuild)
     if prec == "mixed_plain":
         ctx.set_option("refine", 0)
     ctx.set_option("batched", 1 if batched else 0)
@@ -212,3 +214,20 @@ def test_persistent_equals_grouped(torch_cuda, prec):
     assert np.array_equal(a[0], b[0])
     for x, y in zip(a[3], b[3]):
         assert np.array_equal(x, y)
+
+
+def test_rebuilt_tables_give_the_same_sweep(torch_cuda):
+    """Rebuilding the batch tables as samples finish (the default at 3/4 of
+    the batch, and at every finished sample) gives the same bits as never
+    rebuilding: each sample's blocks and reductions are its own."""
+    torch = torch_cuda
+    say("case batch rebuild")
+    a = run(torch, "fp64", batched=True, graph=True, rebuild=0.0)
+    b = run(torch, "fp64", batched=True, graph=True, rebuild=0.75)
+    c = run(torch, "fp64", batched=True, graph=True, rebuild=0.99)
+    for r in (b, c):
+        assert r[2] == a[2]
+        assert np.array_equal(a[1], r[1])
+        assert np.array_equal(a[0], r[0])
+        for x, y in zip(a[3], r[3]):
+            assert np.array_equal(x, y)
