@@ -4,11 +4,16 @@ and 60 mT along z + 2 degrees, in FP64 and in the mixed form (FP32
 convolution with its defect correction) side by side (full 3-D demag path,
 paper Sec. 2 stop rule, tol 1e-6).
 
-Per field: both forms converge; the mixed state is stationary for the FP64
-effective field (torque < 2 tol: cross-stationarity) and lies within 1e-3 of
-the FP64 state (|dm|_inf: the two land in the same basin over these fields;
-measured <= 1e-4); the oracle's own torque at the FP64 states of the first
-and last field is below tol (its FFT convolution at 256^3).  Beyond 60 mT a
+Per field: both forms converge and the mixed state is stationary for the
+FP64 effective field (torque < 2 tol: cross-stationarity).  At H = 0 the
+relaxation from the random start is path dependent: a different rounding
+order (FP32 against FP64, or two FP64 kernels that contract multiply-adds
+differently) can end in a different multi-domain state, each stationary, so
+the states are not compared there; the mixed form then continues from the
+FP64 state.  From there on the two follow one branch: at every field step
+the mixed state lies within 1e-3 of the FP64 state (|dm|_inf, measured
+<= 1e-4).  The oracle's own torque at the FP64 states of the first and last
+field is below tol (its FFT convolution at 256^3).  Beyond 60 mT a
 switching event can send the two forms into mirror-image metastable states
 (the energy is symmetric under y -> -y with the field in the x-z plane;
 which one a run reaches follows its rounding path), so the test stops
@@ -67,8 +72,11 @@ def test_cube_sweep_mixed_against_fp64(torch_cuda):
         say("  field %d: iters fp64 %d mixed %d, |dm|_inf %.2e, mixed torque (FP64 field) %.2e"
             % (f, out["fp64"][1], out["mixed"][1], dm, T))
         assert T < 2 * w["tol"]
-        assert dm < 1e-3
-        assert np.max(np.abs(out["fp64"][0] - out["mixed"][0])) < 1e-4
+        if f == 0:
+            m["mixed"].copy_(m["fp64"])
+        else:
+            assert dm < 1e-3
+            assert np.max(np.abs(out["fp64"][0] - out["mixed"][0])) < 1e-4
         if f in (0, len(F) - 1):
             keep[f] = (H.copy(), m["fp64"].cpu().numpy())
     for c in ctx.values():
