@@ -12,7 +12,9 @@ exercised as in a hysteresis sweep.  Inputs are resident in HBM before the
 clock starts.
 
 With --workload cube the same measurement runs on the 128^3 cube of 2 nm
-cells (full 3-D demag path, random start, 60 mT at 2 degrees from z).
+cells (full 3-D demag path, random start, 60 mT at 2 degrees from z); the
+default film line carries a shorter run of it as "cube" (FP64 and mixed
+iterations/s, the FP64 iteration's algorithmic bytes and rate).
 
 The line also carries "batched": 64 uneven thin platelets (64..256 x
 32..128 x 1..2 cells) swept through every 10th field of their +-40 mT loop,
@@ -64,6 +66,9 @@ def parse():
     p.add_argument("--workload", choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS),
                    default="film")
     p.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    p.add_argument("--no-cube", action="store_true",
+                   help="skip the 128^3 cube leg of the default film line")
+    p.add_argument("--cube-steps", type=int, default=300)
     p.add_argument("--graph", action="store_true",
                    help="with --quick: also time the run with captured HIP graphs")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -130,6 +135,30 @@ def run_gpu(prec, steps, warmup, w, profile, field=0, graph=False, rows=0, yz=-1
     ctx.close()
     return {"iters": r["iters"], "evals": r["heff_evals"], "seconds": dt, "prof": prof,
             "bytes": kb, "torque": r["torque"], "rows_per_block": rows, "yz_variant": yz_var}
+
+
+def cube_leg(steps):
+    """The 128^3 cube (3-D demag path) timed beside the film: FP64 and mixed
+    iterations/s, and the FP64 iteration's algorithmic bytes and rate from a
+    second run with events around every kernel."""
+    import synth
+    wid, field, desc, padded = WORKLOADS["cube"]
+    w = synth.workload(wid)
+    warm = max(10, steps // 10)
+    r64 = run_gpu("fp64", steps, warm, w, profile=None, field=field)
+    rp = run_gpu("fp64", steps, warm, w, profile="all", field=field)
+    rmx = run_gpu("mixed", steps, warm, w, profile=None, field=field)
+    prof = rp["prof"]
+    per_iter = sum(r64["bytes"][k] * v[1] / rp["iters"] for k, v in prof.items() if v[1] > 0)
+    ips = r64["iters"] / r64["seconds"]
+    mips = rmx["iters"] / rmx["seconds"]
+    return {"workload": desc, "padded_grid": padded, "value": ips, "unit": "iters/s",
+            "steps": steps, "ms_per_step": 1e3 * r64["seconds"] / r64["iters"],
+            "model_bytes": per_iter, "model_GBps": per_iter * ips / 1e9,
+            "model_frac_of_8TBps": per_iter * ips / 8e12,
+            "kernel_avg_us_all_timed": {k: 1e3 * v[0] / max(v[1], 1)
+                                        for k, v in prof.items() if v[1] > 0},
+            "mixed": {"value": mips, "unit": "iters/s", "speedup_vs_fp64": mips / ips}}
 
 
 def stored_traffic(prec, kernel, workload):
@@ -519,6 +548,8 @@ def main():
                 "kernel_avg_us_all_timed": {k: 1e3 * v[0] / max(v[1], 1)
                                             for k, v in other_prof.items() if v[1] > 0}},
     }
+    if a.workload == "film" and not a.no_cube:
+        out["cube"] = cube_leg(a.cube_steps)
     if not a.no_batched:
         ib, tb, rcb, nf, bst = run_batched(torch, True)
         iseq, tseq, rcs, _, _ = run_batched(torch, False)
