@@ -315,7 +315,16 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * by one; results are the same either way), "batch_rebuild" (default 0.75:
  * in batched sweeps, once the running samples are at most this fraction of
  * the batch, its work tables are rebuilt from the running ones and the
- * graph captured again; 0 never; results are the same either way).
+ * graph captured again; 0 never; results are the same either way),
+ * "fused_finish" (default 1: in mm_minimize_to_tol and in sweeps, a
+ * sample's forward x pass of the wave-FFT lengths takes the previous
+ * iteration's finish (the reduction of the per-block sums, the stop rule
+ * and the step of eq. (12)) over instead of a one-block finish kernel: its
+ * block 0 reduces and decides, the other blocks wait for the published
+ * step after issuing their first loads; every poll interval still ends
+ * with a finish kernel; not with the line search or a two-stage
+ * reduction (more than 2048 per-block sums); 0: a finish kernel after
+ * every iteration; results are the same either way).
  * Unknown keys or values give MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 

@@ -89,6 +89,7 @@ struct Sample {
   double* mref = nullptr;
   double* hdref = nullptr;
   long long ref_age = 0;      // iterations since the last reference pass
+  bool fin_pending = false;   // the last inverse pass's sums await their finish
   // line search: saved base state and the trial's gradient (on first use)
   double* ls_mbase = nullptr;
   void* ls_g2 = nullptr;      // transform type, like g
@@ -96,7 +97,7 @@ struct Sample {
   // the m buffer, batch length, correction flag and material it was made with
   hipGraphExec_t it_graph = nullptr;
   const double* it_graph_m = nullptr;
-  int it_graph_n = 0, it_graph_ref = 0, it_graph_mat = -1, it_graph_ls = 0;
+  int it_graph_n = 0, it_graph_ref = 0, it_graph_mat = -1, it_graph_ls = 0, it_graph_fuse = 0;
   int mat_version = 0;
   int64_t evals_total = 0, iters_total = 0;
 };
@@ -134,6 +135,8 @@ struct mm_ctx {
   int persistent = 1;           // batched passes: one persistent launch per pass (per
                                 // layer count for yz); 0: one launch per group of
                                 // equal transform lengths
+  int fused_finish = 1;         // single-sample runs: the next forward x pass takes each
+                                // iteration's finish over (0: a finish kernel each)
   // auxiliary streams (default priority) and fork/join events of the
   // batched passes, made on first use
   std::vector<hipStream_t> aux;
@@ -477,6 +480,7 @@ struct EvalOut {
   const int* done = nullptr;  // flag that skips the demag and local passes
   void* spec = nullptr;       // spectrum buffer in place of the sample's (NULL: its own)
   void* B = nullptr;          // 3-D path: y-transformed spectrum likewise
+  int fuse_q = -1;            // >= 0: batch position of a fused-finish iteration
 };
 
 LocalArgs local_args(const Sample& s, bool unit_A = false, bool zeeman = true) {
@@ -583,9 +587,19 @@ void enqueue_demag_mid(mm_ctx* c, const Sample& s, const Conv& v, const int* don
   c->prof = prof;
 }
 
+// The finish of the last iteration if its sums still await it (left by a
+// fused-finish iteration): before anything reads the state.
+void flush_finish(mm_ctx* c, Sample& s) {
+  if (!s.fin_pending) return;
+  s.fin_pending = false;
+  Timer t(c, KID_FINISH);
+  launch_finish(c->stream, s.partials, s.nb3, s.st, s.Ms, s.V);
+}
+
 // Reference pass of the defect correction: mref = m (no pending update is
 // applied) and hdref = H_d(mref) in double precision.
 void enqueue_reference(mm_ctx* c, Sample& s, const double* m, const MinState* mst) {
+  flush_finish(c, s);
   hipStream_t st = c->stream;
   const Conv v = conv_ref(s);
   const int* done = mst ? &mst->done : nullptr;
@@ -602,9 +616,19 @@ void enqueue_reference(mm_ctx* c, Sample& s, const double* m, const MinState* ms
 
 // m is updated in place when o.iterate and an update is pending.  A
 // minimiser iteration of a single-precision context with a reference
-// transforms m - mref and adds hdref.
+// transforms m - mref and adds hdref.  o.fuse_q >= 0 (an iteration at that
+// position of a batch that ends with flush_finish): the forward x pass takes
+// the previous iteration's finish over and this iteration's is left pending.
 void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
+  if (o.fuse_q <= 0) flush_finish(c, s);
   hipStream_t st = c->stream;
+  FinFuse fz{nullptr, nullptr, s.Ms, s.V, s.nb3, 0};
+  if (o.fuse_q >= 0) {
+    fz.st = s.st;
+    fz.par = o.fuse_q & 1;
+    if (o.fuse_q > 0 && s.fin_pending) fz.partials = s.partials;
+    s.fin_pending = false;
+  }
   MinState* mst = o.iterate ? s.st : nullptr;
   const int* done = mst ? &mst->done : o.done;
   double* mm = const_cast<double*>(m);
@@ -619,10 +643,10 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
     Timer t(c, KID_XF);
     if (v.sp)
       launch_xf<float>(st, mm, as<float>(gx), as<float>(sx), mst, s.nx, s.ny, s.nz, s.Px, v.R,
-                       v.spec, v.twx, corr ? s.mref : nullptr, nullptr);
+                       v.spec, v.twx, corr ? s.mref : nullptr, nullptr, &fz);
     else
       launch_xf<double>(st, mm, as<double>(gx), as<double>(sx), mst, s.nx, s.ny, s.nz, s.Px, v.R,
-                        v.spec, v.twx, nullptr, nullptr);
+                        v.spec, v.twx, nullptr, nullptr, &fz);
   }
   enqueue_demag_mid(c, s, v, done, true);
   LocalArgs a = local_args(s, o.unit_A, o.zeeman);
@@ -646,18 +670,32 @@ void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
       launch_xil<double>(st, v.spec, a, s.Px, v.R, o.Hd, part, v.twx);
   }
   if (o.st_fin) {
-    Timer t(c, KID_FINISH);
-    launch_finish(st, s.partials, s.nb3, o.st_fin, s.Ms, s.V);
+    if (o.fuse_q >= 0) {
+      s.fin_pending = true;
+    } else {
+      Timer t(c, KID_FINISH);
+      launch_finish(st, s.partials, s.nb3, o.st_fin, s.Ms, s.V);
+    }
   }
+}
+
+// Whether the sample's forward x pass can take the finish over: the wave
+// pass, sums reduced in one stage, no line search (whose trial logic reads
+// more of the state in the forward pass).
+bool fuse_ok(const mm_ctx* c, const Sample& s) {
+  return c->fused_finish && !c->ls.on && xf_fuses_finish(s.Px) &&
+         s.nb3 <= finish_single_stage_max();
 }
 
 // One minimiser iteration; with the defect correction, a reference pass
 // first whenever the reference is poll_every iterations old (or stale).
-void enqueue_iteration(mm_ctx* c, Sample& s, double* m) {
+// q >= 0: position in a batch of iterations that ends with flush_finish.
+void enqueue_iteration(mm_ctx* c, Sample& s, double* m, int q = -1) {
   if (use_ref(c, s) && s.ref_age >= c->poll_every) enqueue_reference(c, s, m, s.st);
   EvalOut o;
   o.iterate = true;
   o.st_fin = s.st;
+  o.fuse_q = q >= 0 && fuse_ok(c, s) ? q : -1;
   enqueue_eval(c, s, m, o);
   ++s.ref_age;
 }
@@ -1294,6 +1332,7 @@ int status_of(int done) {
 }
 
 int read_state(mm_ctx* c, Sample& s) {
+  flush_finish(c, s);
   HIPCHK(c, hipMemcpyAsync(s.st_host, s.st, sizeof(MinState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return MM_OK;
@@ -1306,7 +1345,8 @@ int read_state(mm_ctx* c, Sample& s) {
 int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
   const int ref = use_ref(c, s) ? 1 : 0;
   if (s.it_graph && s.it_graph_m == m && s.it_graph_n == c->poll_every && s.it_graph_ref == ref &&
-      s.it_graph_mat == s.mat_version && s.it_graph_ls == c->ls.on)
+      s.it_graph_mat == s.mat_version && s.it_graph_ls == c->ls.on &&
+      s.it_graph_fuse == (fuse_ok(c, s) ? 1 : 0))
     return MM_OK;
   if (s.it_graph) (void)hipGraphExecDestroy(s.it_graph);
   s.it_graph = nullptr;
@@ -1314,7 +1354,8 @@ int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
   s.ref_age = kRefStale;
   hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, s, m);
+    for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, s, m, q);
+    flush_finish(c, s);
     e = hipStreamEndCapture(c->stream, &g);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&s.it_graph, g, nullptr, nullptr, 0);
@@ -1328,6 +1369,7 @@ int ensure_iter_graph(mm_ctx* c, Sample& s, double* m) {
   s.it_graph_ref = ref;
   s.it_graph_mat = s.mat_version;
   s.it_graph_ls = c->ls.on;
+  s.it_graph_fuse = fuse_ok(c, s) ? 1 : 0;
   return MM_OK;
 }
 
@@ -1371,13 +1413,16 @@ int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm
       HIPCHK(c, hipGraphLaunch(s.it_graph, c->stream));
       s.ref_age = c->poll_every;   // as after an eager batch
     } else {
-      for (long long q = 0; q < batch; ++q) enqueue_iteration(c, s, m);
+      for (long long q = 0; q < batch; ++q) enqueue_iteration(c, s, m, (int)q);
+      flush_finish(c, s);
     }
     left -= batch;
     HIPCHK(c, hipGetLastError());
     int rc = read_state(c, s);
     if (rc != MM_OK) return rc;
     prof_collect(c);
+    if (s.st_host->fin_err != 0)
+      return fail(c, MM_ESTATE, "a forward x pass gave up waiting for the finish decision");
     if (s.st_host->done != 0) break;
     // the evaluation that reaches max_iter ends the run on the device; a
     // state that still runs well after it would keep the host polling
@@ -1930,7 +1975,8 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
     }
     for (int k = 0; k < S; ++k) {
       if (!running[k] || in_batch[k]) continue;
-      for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, c->smp[k], m[k]);
+      for (int q = 0; q < c->poll_every; ++q) enqueue_iteration(c, c->smp[k], m[k], q);
+      flush_finish(c, c->smp[k]);
     }
     ++polls;
     eager = false;
@@ -1945,6 +1991,11 @@ int mm_hysteresis_sweep(mm_ctx* c, double* const* m, const double* H, int n_fiel
       return fail(c, MM_EHIP, std::string("sweep: ") + hipGetErrorString(e));
     }
     prof_collect(c);
+    for (int k = 0; k < S; ++k)
+      if (running[k] && c->smp[k].st_host->fin_err != 0) {
+        cleanup();
+        return fail(c, MM_ESTATE, "a forward x pass gave up waiting for the finish decision");
+      }
     for (int k = 0; k < S; ++k)
       if (running[k] && c->smp[k].st_host->done != 0) {
         running[k] = 0;
@@ -2041,6 +2092,8 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->batch_rebuild = value;
   } else if (!std::strcmp(key, "persistent")) {
     c->persistent = value != 0.0;
+  } else if (!std::strcmp(key, "fused_finish")) {
+    c->fused_finish = value != 0.0;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
   } else if (!std::strcmp(key, "yz_variant")) {

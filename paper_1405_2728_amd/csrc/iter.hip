@@ -212,15 +212,54 @@ template <int VL>
 __host__ __device__ constexpr int wx_region() { return wx_region_of(VL); }
 __device__ __forceinline__ int wx_pad(int k) { return k + (k >> 3); }
 
+// The previous iteration's finish taken over by a forward x pass (FinFuse,
+// partials set).  Block 0 reduces the sums and decides (the finish kernel's
+// order and arithmetic), then publishes the word the pass needs; every
+// other block's thread 0 polls for it.  Both return the word in every
+// thread of the block (block-uniform; they contain block barriers).
+__device__ __forceinline__ double fin_decide(const FinFuse& fz) {
+  __shared__ double s_w;
+  __shared__ double scratch[kNPartial * kXwThreads / 64];
+  finish_in_block<kXwThreads, 1>(fz.partials, fz.nb, fz.st, fz.Ms, fz.V, scratch);
+  if (threadIdx.x == 0) {
+    const MinState* st = fz.st;   // this thread's own writes of the decision
+    const double w = st->done != 0 ? kFinStop : (st->pending != 0 ? st->last_tau : kFinNoUpdate);
+    __hip_atomic_store(&fz.st->fin_slot[fz.par], (unsigned long long)__double_as_longlong(w),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_w = w;
+  }
+  __syncthreads();
+  return s_w;
+}
+
+__device__ __forceinline__ double fin_wait(const FinFuse& fz) {
+  __shared__ double s_w;
+  if (threadIdx.x == 0) {
+    unsigned long long* slot = &fz.st->fin_slot[fz.par];
+    unsigned long long b = kFinSent;
+    for (int n = 0; n < kFinSpin; ++n) {
+      b = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (b != kFinSent) break;
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (b == kFinSent) {   // gave up: this block writes nothing; the host reports it
+      __hip_atomic_store(&fz.st->fin_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      b = (unsigned long long)__double_as_longlong(kFinStop);
+    }
+    s_w = __longlong_as_double((long long)b);
+  }
+  __syncthreads();
+  return s_w;
+}
+
 // Body of the forward x pass for logical block L (rows z, y0 .. y0+R-1).
 template <typename T, int VL>
 __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __restrict__ g,
-                                          T* __restrict__ sbuf,
-                                          const MinState* __restrict__ st, int nx, int ny, int nz,
-                                          int R, cx<T>* __restrict__ out,
+                                          T* __restrict__ sbuf, const MinState* st, int nx,
+                                          int ny, int nz, int R, cx<T>* __restrict__ out,
                                           const cx<T>* __restrict__ twx, int L,
                                           const double* __restrict__ msub,
-                                          double* __restrict__ mcopy) {
+                                          double* __restrict__ mcopy, const FinFuse& fz) {
   constexpr int M = 64 * VL;
   constexpr int NG = 8 * VL;
   constexpr int RG = wx_region<VL>();
@@ -240,11 +279,6 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
     mbase = st->ls_mbase;
     g2 = static_cast<const T*>(st->ls_g2);
   }
-  const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
-  // line search: the trial starts from the saved base (retry) or from the
-  // accepted state in m with the gradient of its evaluation in g2, which
-  // then become the saved base (mbase, g)
-  const bool ls_upd = upd && ls != 0;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem);
   T* smr = reinterpret_cast<T*>(smem);
@@ -263,8 +297,8 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
     constexpr int U = 4;                       // cells in flight per thread
     const int total = rows * nx;
     const size_t row0 = ((size_t)z * ny + y0) * nx;   // rows of the block are contiguous
-    for (int base = first; base < total; base += U * nthr) {
-      double mi[U][3], gi[U][3];
+    double mi[U][3], gi[U][3];
+    auto load = [&](int base) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int idx = base + u * nthr;
@@ -276,6 +310,33 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
           }
         }
       }
+    };
+    // block 0 clears the slot of the next pass; with a finish to take over,
+    // its decision replaces the state read above (blocks other than 0 issue
+    // their first cells' loads before they wait for it)
+    bool prefetched = false;
+    if (fz.st != nullptr) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) fz.st->fin_slot[fz.par ^ 1] = kFinSent;
+      if (fz.partials != nullptr) {
+        double w;
+        if (blockIdx.x == 0) {
+          w = fin_decide(fz);
+        } else {
+          load(first);
+          prefetched = true;
+          w = fin_wait(fz);
+        }
+        done = w == kFinStop ? 1 : 0;
+        pend = w > 0.0 ? 1 : 0;
+        tau = w;
+      }
+    }
+    const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
+    // line search: the trial starts from the saved base (retry) or from the
+    // accepted state in m with the gradient of its evaluation in g2, which
+    // then become the saved base (mbase, g)
+    const bool ls_upd = upd && ls != 0;
+    auto process = [&](int base) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int idx = base + u * nthr;
@@ -317,6 +378,16 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
         for (int c = 0; c < 3; ++c)
           smr[2 * ((size_t)(r * 3 + c) * RG + (x >> 1)) + (x & 1)] = (T)mi[u][c];
       }
+    };
+    // the first pass's cells were loaded before the wait (blocks other than 0)
+    int base = first;
+    if (prefetched) {
+      if (base < total) process(base);
+      base += U * nthr;
+    }
+    for (; base < total; base += U * nthr) {
+      load(base);
+      process(base);
     }
   }
   if (done != 0) return;
@@ -377,11 +448,11 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
 template <typename T, int VL>
 __global__ void __launch_bounds__(kXwThreads)
 k_xf_w(double* __restrict__ m, const T* __restrict__ g, T* __restrict__ sbuf,
-       const MinState* __restrict__ st, int nx, int ny, int nz, int R,
-       cx<T>* __restrict__ out, const cx<T>* __restrict__ twx, const double* __restrict__ msub,
-       double* __restrict__ mcopy) {
+       const MinState* st, int nx, int ny, int nz, int R, cx<T>* __restrict__ out,
+       const cx<T>* __restrict__ twx, const double* __restrict__ msub,
+       double* __restrict__ mcopy, FinFuse fz) {
   xf_w_body<T, VL>(m, g, sbuf, st, nx, ny, nz, R, out, twx, xcd_remap(blockIdx.x, gridDim.x),
-                   msub, mcopy);
+                   msub, mcopy, fz);
 }
 
 // Body of the inverse x pass with the local terms for logical block L.
@@ -525,9 +596,10 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
 // Logical block `block` of sample d's forward x pass.
 template <typename T, int VL>
 __device__ __forceinline__ void xf_desc(const BatchDesc& d, int block) {
+  const FinFuse none{nullptr, nullptr, 0.0, 0.0, 0, 0};
   xf_w_body<T, VL>(d.m, static_cast<const T*>(d.g), static_cast<T*>(d.s), d.st, d.nx, d.ny,
                    d.nz, d.R, (cx<T>*)d.spec, (const cx<T>*)d.twx, block,
-                   d.pass == 1 ? d.mref : nullptr, d.pass == 2 ? d.mref : nullptr);
+                   d.pass == 1 ? d.mref : nullptr, d.pass == 2 ? d.mref : nullptr, none);
 }
 
 template <typename T, int VL>
@@ -664,13 +736,13 @@ int rows_per_block(int M, int ny, bool single) {
 template <typename T, int VL>
 static void xf_wave(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st,
                     int nx, int ny, int nz, int R, void* out, const void* twx, const double* msub,
-                    double* mcopy) {
+                    double* mcopy, const FinFuse& fz) {
   const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
   const int nb = nz * ((ny + R - 1) / R);
   auto k = k_xf_w<T, VL>;
   set_lds(k, lds);
   hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, m, g, sbuf, st, nx, ny, nz, R,
-                     (cx<T>*)out, (const cx<T>*)twx, msub, mcopy);
+                     (cx<T>*)out, (const cx<T>*)twx, msub, mcopy, fz);
 }
 
 template <typename T, int VL>
@@ -684,20 +756,27 @@ static void xil_wave(hipStream_t s, const void* in, const LocalArgs& a, int R, d
                      (const cx<T>*)twx);
 }
 
+// the wave-FFT forward pass (half lengths 64 VL, VL = 1..8) takes the finish over
+bool xf_fuses_finish(int Px) {
+  const int M = Px / 2;
+  return Px % 2 == 0 && M % 64 == 0 && M >= 64 && M <= 512;
+}
+
 template <typename T>
 void launch_xf(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st, int nx, int ny,
                int nz, int Px, int R, void* out, const void* twx, const double* msub,
-               double* mcopy) {
+               double* mcopy, const FinFuse* fzp) {
+  const FinFuse fz = fzp != nullptr ? *fzp : FinFuse{nullptr, nullptr, 0.0, 0.0, 0, 0};
   const int M = Px / 2;
   switch (M) {
-    case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 128: xf_wave<T, 2>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 192: xf_wave<T, 3>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 256: xf_wave<T, 4>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 320: xf_wave<T, 5>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 384: xf_wave<T, 6>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 448: xf_wave<T, 7>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
-    case 512: xf_wave<T, 8>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy); return;
+    case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 128: xf_wave<T, 2>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 192: xf_wave<T, 3>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 256: xf_wave<T, 4>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 320: xf_wave<T, 5>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 384: xf_wave<T, 6>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 448: xf_wave<T, 7>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
+    case 512: xf_wave<T, 8>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;
     default: break;
   }
   const long long vals = 3LL * R * M;
@@ -823,9 +902,11 @@ template void launch_x_persistent<float>(hipStream_t, bool, const BatchDesc*, co
 template void launch_x_batched<float>(hipStream_t, bool, const BatchDesc*, const WorkItem*, int,
                                       int, int);
 template void launch_xf<double>(hipStream_t, double*, const double*, double*, const MinState*, int,
-                                int, int, int, int, void*, const void*, const double*, double*);
+                                int, int, int, int, void*, const void*, const double*, double*,
+                                const FinFuse*);
 template void launch_xf<float>(hipStream_t, double*, const float*, float*, const MinState*, int,
-                               int, int, int, int, void*, const void*, const double*, double*);
+                               int, int, int, int, void*, const void*, const double*, double*,
+                               const FinFuse*);
 template void launch_xil<double>(hipStream_t, const void*, const LocalArgs&, int, int, double*,
                                  double*, const void*);
 template void launch_xil<float>(hipStream_t, const void*, const LocalArgs&, int, int, double*,

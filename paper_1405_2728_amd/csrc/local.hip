@@ -17,73 +17,18 @@
 
 namespace mmk {
 
-// One block: reduce the per-block sums in a fixed order (each thread sums
-// rows tid, tid + T, ... with kFinishRows rows in flight), then (thread 0)
-// the stop rule, the step size of eq. (12) and the iteration counters.
-constexpr int kFinishThreads = 256;
-constexpr int kFinishRows = 4;
-
-// rows b0, b0 + T, ..., b0 + (kFinishRows - 1) T, those past the end
-// clamped to the last row (dropped again by finish_add)
-__device__ __forceinline__ void finish_load(const double* __restrict__ partials, int nb, int b0,
-                                            double (&x)[kFinishRows][kNPartial]) {
-#pragma unroll
-  for (int u = 0; u < kFinishRows; ++u) {
-    const int b = min(b0 + u * kFinishThreads, nb - 1);
-#pragma unroll
-    for (int q = 0; q < kNPartial; ++q) x[u][q] = partials[(size_t)b * kNPartial + q];
-  }
-}
-
-// add the loaded rows in row order; rows past the end are dropped by a
-// select, not a branch, so that all the loads stay in flight together
-__device__ __forceinline__ void finish_add(int nb, int b0,
-                                           const double (&x)[kFinishRows][kNPartial],
-                                           double (&v)[kNPartial]) {
-#pragma unroll
-  for (int u = 0; u < kFinishRows; ++u) {
-    const bool ok = b0 + u * kFinishThreads < nb;
-#pragma unroll
-    for (int q = 0; q < kNPartial; ++q) {
-      const double t = q == kPartMax ? fmax(v[q], x[u][q]) : v[q] + x[u][q];
-      v[q] = ok ? t : v[q];
-    }
-  }
-}
-
-__device__ __forceinline__ void finish_block(const double* __restrict__ partials, int nb,
-                                             MinState* __restrict__ st, double Ms, double V) {
-  __shared__ double scratch[kNPartial * kFinishThreads / 64];
-  double x[kFinishRows][kNPartial];
-  finish_load(partials, nb, threadIdx.x, x);
-  // the state is read while the first rows' loads are in flight
-  const int dn = st->done;
-  const FinishIn f = load_finish_in(st);
-  double v[kNPartial] = {};
-  finish_add(nb, threadIdx.x, x, v);
-  for (int b0 = threadIdx.x + kFinishRows * kFinishThreads; b0 < nb;
-       b0 += kFinishRows * kFinishThreads) {
-    finish_load(partials, nb, b0, x);
-    finish_add(nb, b0, x, v);
-  }
-  if (dn != 0) return;
-  bool is_max[kNPartial];
-  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
-  block_reduce<kFinishThreads>(v, is_max, scratch);
-  if (threadIdx.x != 0) return;
-  finish_decision(st, f, v, Ms, V);
-}
-
 __global__ void __launch_bounds__(kFinishThreads) k_finish(const double* __restrict__ partials,
                                                            int nblocks, MinState* __restrict__ st,
                                                            double Ms, double V) {
-  finish_block(partials, nblocks, st, Ms, V);
+  __shared__ double scratch[kNPartial * kFinishThreads / 64];
+  finish_in_block<kFinishThreads, kFinishRows>(partials, nblocks, st, Ms, V, scratch);
 }
 
 // Batched: block b finishes sample b of the table.
 __global__ void __launch_bounds__(kFinishThreads) k_finish_b(const BatchDesc* __restrict__ descs) {
+  __shared__ double scratch[kNPartial * kFinishThreads / 64];
   const BatchDesc& d = descs[blockIdx.x];
-  finish_block(d.partials, d.nb3, d.st, d.Ms, d.V);
+  finish_in_block<kFinishThreads, kFinishRows>(d.partials, d.nb3, d.st, d.Ms, d.V, scratch);
 }
 
 // Apply a pending midpoint update (eq. (7)) to m and store s = m+ - m.
@@ -180,6 +125,8 @@ __global__ void k_reset_state(MinState* st, double tau0, double tol, long long m
   z.ls_C = z.ls_Q = z.ls_G = 0.0;
   z.ls_mbase = ls_mbase;
   z.ls_g2 = ls_g2;
+  z.fin_slot[0] = z.fin_slot[1] = kFinSent;
+  z.fin_err = 0;
   *st = z;
 }
 
@@ -258,6 +205,8 @@ k_finish_stage1(const double* __restrict__ partials, int nb, double* __restrict_
     for (int q = 0; q < kNPartial; ++q) out[(size_t)blockIdx.x * kNPartial + q] = v[q];
   }
 }
+
+int finish_single_stage_max() { return kFinishDirect; }
 
 int finish_extra_rows(int nblocks) {
   return nblocks > kFinishDirect ? (nblocks + kFinishThreads - 1) / kFinishThreads : 0;

@@ -295,6 +295,74 @@ __device__ __forceinline__ void finish_decision(MinState* st, const FinishIn& f,
   st->pending = 1;
 }
 
+// One block reduces the per-block sums partials[nb][kNPartial] in a fixed
+// order (thread t < kFinishThreads sums rows t, t + T, ... in row order,
+// kFinishRows rows in flight; then block_reduce), and thread 0 takes the
+// decision: the stop rule, the step size of eq. (12) and the iteration
+// counters.  Threads t >= kFinishThreads of a larger block (the forward x
+// pass that takes the finish over) add nothing: their waves' zeros come last
+// in block_reduce's wave order, so the result is the finish kernel's.
+constexpr int kFinishThreads = 192;
+constexpr int kFinishRows = 4;
+
+// rows b0, b0 + T, ..., b0 + (ROWS - 1) T, those past the end clamped to the
+// last row (dropped again by finish_add)
+template <int ROWS>
+__device__ __forceinline__ void finish_load(const double* __restrict__ partials, int nb, int b0,
+                                            double (&x)[ROWS][kNPartial]) {
+#pragma unroll
+  for (int u = 0; u < ROWS; ++u) {
+    const int b = min(b0 + u * kFinishThreads, nb - 1);
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) x[u][q] = partials[(size_t)b * kNPartial + q];
+  }
+}
+
+// add the loaded rows in row order; rows past the end are dropped by a
+// select, not a branch, so that all the loads stay in flight together
+template <int ROWS>
+__device__ __forceinline__ void finish_add(int nb, int b0, const double (&x)[ROWS][kNPartial],
+                                           double (&v)[kNPartial]) {
+#pragma unroll
+  for (int u = 0; u < ROWS; ++u) {
+    const bool ok = b0 + u * kFinishThreads < nb;
+#pragma unroll
+    for (int q = 0; q < kNPartial; ++q) {
+      const double t = q == kPartMax ? fmax(v[q], x[u][q]) : v[q] + x[u][q];
+      v[q] = ok ? t : v[q];
+    }
+  }
+}
+
+// ROWS: rows in flight per thread (registers against latency); the sums do
+// not depend on it, each thread adding its rows in row order.
+template <int MAXT, int ROWS, int NS>
+__device__ __forceinline__ void finish_in_block(const double* __restrict__ partials, int nb,
+                                                MinState* st, double Ms, double V,
+                                                double (&scratch)[NS]) {
+  const int t = threadIdx.x;
+  const bool act = t < kFinishThreads;
+  double x[ROWS][kNPartial];
+  if (act) finish_load<ROWS>(partials, nb, t, x);
+  // the state is read while the first rows' loads are in flight
+  const int dn = st->done;
+  const FinishIn f = load_finish_in(st);
+  double v[kNPartial] = {};
+  if (act) {
+    finish_add<ROWS>(nb, t, x, v);
+    for (int b0 = t + ROWS * kFinishThreads; b0 < nb; b0 += ROWS * kFinishThreads) {
+      finish_load<ROWS>(partials, nb, b0, x);
+      finish_add<ROWS>(nb, b0, x, v);
+    }
+  }
+  if (dn != 0) return;
+  bool is_max[kNPartial];
+  for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
+  block_reduce<MAXT>(v, is_max, scratch);
+  if (t != 0) return;
+  finish_decision(st, f, v, Ms, V);
+}
+
 // Midpoint step: m+ = (I - [b]x)^-1 (I + [b]x) m with b = (tau/2) m x H
 // = -(tau/2) m x g for |m| = 1, i.e. m+ = m + 2 (b x m + b x (b x m)) /
 // (1 + |b|^2), followed by renormalisation.

@@ -66,7 +66,34 @@ struct MinState {
   double ls_C, ls_Q, ls_G;
   double* ls_mbase;
   void* ls_g2;         // values of the transform type, like g
+  // Finish taken over by the next forward x pass (FinFuse): the decision of
+  // the pass is published in fin_slot[parity] (kFinSent until then);
+  // fin_err is set if a block gave up waiting for it
+  unsigned long long fin_slot[2];
+  int fin_err;
 };
+
+// Finish of the previous iteration taken over by the next forward x pass of
+// a single-sample minimiser run.  Block 0 of the pass reduces the previous
+// inverse pass's per-block sums in the finish kernel's order, takes the
+// decision (stop rule, step of eq. (12)) into the state and publishes what
+// the pass needs (stop, no update, or the step) in st->fin_slot[par]; the
+// other blocks issue their first loads, then wait for it.  partials == NULL:
+// nothing to take over (the first pass after a finish kernel), block 0 only
+// resets st->fin_slot[par ^ 1] for the next pass.  st == NULL: off.
+struct FinFuse {
+  MinState* st;
+  const double* partials;
+  double Ms, V;
+  int nb, par;
+};
+// published words: a signalling NaN (never an arithmetic result) until the
+// decision, -1 stop, -2 no update, else the step tau > 0
+constexpr unsigned long long kFinSent = 0x7FF4000000000001ull;
+constexpr double kFinStop = -1.0, kFinNoUpdate = -2.0;
+// polls of the slot before a block gives up (fin_err), with a short sleep
+// between them: far beyond any finish (microseconds)
+constexpr int kFinSpin = 1 << 22;
 
 // Conjugate-gradient state of an adjoint solve, resident in device memory.
 struct CGState {
@@ -261,11 +288,16 @@ void launch_clear_pending(hipStream_t s, MinState* st);
 // fused x passes of the thin-film iteration
 int rows_per_block(int M, int ny, bool single);
 // msub (NULL: none) is subtracted from m before the transform; mcopy (NULL:
-// none) receives a copy of m, and then no pending update is applied
+// none) receives a copy of m, and then no pending update is applied.  fz
+// (NULL or fz->st NULL: none) hands the previous iteration's finish to the
+// pass; only the wave-FFT lengths take it (xf_fuses_finish).
 template <typename T>
 void launch_xf(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st, int nx, int ny,
                int nz, int Px, int R, void* out, const void* twx, const double* msub,
-               double* mcopy);
+               double* mcopy, const FinFuse* fz = nullptr);
+bool xf_fuses_finish(int Px);
+// largest per-block sum count the finish kernel reduces in one stage
+int finish_single_stage_max();
 template <typename T>
 // partials: per-block sums out (NULL: none), reduced by launch_finish
 void launch_xil(hipStream_t s, const void* in, const LocalArgs& a, int Px, int R, double* Hd_out,
