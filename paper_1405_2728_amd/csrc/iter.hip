@@ -253,7 +253,8 @@ __device__ __forceinline__ double fin_wait(const FinFuse& fz) {
 }
 
 // Body of the forward x pass for logical block L (rows z, y0 .. y0+R-1).
-template <typename T, int VL>
+// FUSE: the pass takes the previous iteration's finish over (fz.st set).
+template <typename T, int VL, bool FUSE>
 __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __restrict__ g,
                                           T* __restrict__ sbuf, const MinState* st, int nx,
                                           int ny, int nz, int R, cx<T>* __restrict__ out,
@@ -297,25 +298,130 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
     constexpr int U = 4;                       // cells in flight per thread
     const int total = rows * nx;
     const size_t row0 = ((size_t)z * ny + y0) * nx;   // rows of the block are contiguous
-    double mi[U][3], gi[U][3];
-    auto load = [&](int base) {
+    // one cell of phase 1: line-search base handling, the pending update
+    // (eq. (7)) with s = m+ - m, the copy / subtraction of the reference,
+    // and the sequence value into LDS
+    auto cell = [&](int idx, double (&mi)[3], double (&gi)[3], bool upd, bool ls_upd) {
+      const int r = idx / nx, x = idx - r * nx;
+      const size_t i = row0 + idx;
+      if (ls_upd) {
+        // line search: the trial starts from the saved base (retry) or from
+        // the accepted state in m with the gradient of its evaluation in
+        // g2, which then become the saved base (mbase, g)
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int idx = base + u * nthr;
-        if (idx < total) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            mi[u][c] = m[(size_t)c * N + row0 + idx];
-            gi[u][c] = g != nullptr ? (double)g[(size_t)c * N + row0 + idx] : 0.0;
+        for (int c = 0; c < 3; ++c) {
+          if (retry) {
+            mi[c] = mbase[(size_t)c * N + i];
+          } else {
+            const T gt = g2[(size_t)c * N + i];
+            gi[c] = (double)gt;
+            mbase[(size_t)c * N + i] = mi[c];
+            const_cast<T*>(g)[(size_t)c * N + i] = gt;
           }
         }
       }
+      if (upd) {
+        double mo[3];
+        cayley_step(mi, gi, tau, mo);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          m[(size_t)c * N + i] = mo[c];
+          sbuf[(size_t)c * N + i] = (T)(mo[c] - mi[c]);
+          mi[c] = mo[c];
+        }
+      }
+      if (mcopy != nullptr && done == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mcopy[(size_t)c * N + i] = mi[c];
+      }
+      if (msub != nullptr) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mi[c] -= msub[(size_t)c * N + i];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        smr[2 * ((size_t)(r * 3 + c) * RG + (x >> 1)) + (x & 1)] = (T)mi[c];
     };
-    // block 0 clears the slot of the next pass; with a finish to take over,
-    // its decision replaces the state read above (blocks other than 0 issue
-    // their first cells' loads before they wait for it)
-    bool prefetched = false;
-    if (fz.st != nullptr) {
+    if constexpr (!FUSE) {
+      // the cell code written out in the loop: through the lambda the
+      // compiler holds this pass at 134 VGPRs instead of 128 (3 waves per
+      // SIMD instead of 4)
+      const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
+      const bool ls_upd = upd && ls != 0;
+      for (int base = first; base < total; base += U * nthr) {
+        double mi[U][3], gi[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = base + u * nthr;
+          if (idx < total) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              mi[u][c] = m[(size_t)c * N + row0 + idx];
+              gi[u][c] = g != nullptr ? (double)g[(size_t)c * N + row0 + idx] : 0.0;
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = base + u * nthr;
+          if (idx >= total) continue;
+          const int r = idx / nx, x = idx - r * nx;
+          const size_t i = row0 + idx;
+          if (ls_upd) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              if (retry) {
+                mi[u][c] = mbase[(size_t)c * N + i];
+              } else {
+                const T gt = g2[(size_t)c * N + i];
+                gi[u][c] = (double)gt;
+                mbase[(size_t)c * N + i] = mi[u][c];
+                const_cast<T*>(g)[(size_t)c * N + i] = gt;
+              }
+            }
+          }
+          if (upd) {
+            double mo[3];
+            cayley_step(mi[u], gi[u], tau, mo);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              m[(size_t)c * N + i] = mo[c];
+              sbuf[(size_t)c * N + i] = (T)(mo[c] - mi[u][c]);
+              mi[u][c] = mo[c];
+            }
+          }
+          if (mcopy != nullptr && done == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mcopy[(size_t)c * N + i] = mi[u][c];
+          }
+          if (msub != nullptr) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mi[u][c] -= msub[(size_t)c * N + i];
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            smr[2 * ((size_t)(r * 3 + c) * RG + (x >> 1)) + (x & 1)] = (T)mi[u][c];
+        }
+      }
+    } else {
+      double mi[U][3], gi[U][3];
+      auto load = [&](int base) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = base + u * nthr;
+          if (idx < total) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              mi[u][c] = m[(size_t)c * N + row0 + idx];
+              gi[u][c] = g != nullptr ? (double)g[(size_t)c * N + row0 + idx] : 0.0;
+            }
+          }
+        }
+      };
+      // block 0 clears the slot of the next pass; with a finish to take
+      // over, its decision replaces the state read above (blocks other than
+      // 0 issue their first cells' loads before they wait for it)
+      bool prefetched = false;
       if (blockIdx.x == 0 && threadIdx.x == 0) fz.st->fin_slot[fz.par ^ 1] = kFinSent;
       if (fz.partials != nullptr) {
         double w;
@@ -326,68 +432,26 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
           prefetched = true;
           w = fin_wait(fz);
         }
+        // block-uniform: taken into scalar registers, so that the update's
+        // branches stay uniform as with the state read above
+        const long long wb = __double_as_longlong(w);
+        const int lo = __builtin_amdgcn_readfirstlane((int)(wb & 0xffffffffll));
+        const int hi = __builtin_amdgcn_readfirstlane((int)(wb >> 32));
+        w = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
         done = w == kFinStop ? 1 : 0;
         pend = w > 0.0 ? 1 : 0;
         tau = w;
       }
-    }
-    const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
-    // line search: the trial starts from the saved base (retry) or from the
-    // accepted state in m with the gradient of its evaluation in g2, which
-    // then become the saved base (mbase, g)
-    const bool ls_upd = upd && ls != 0;
-    auto process = [&](int base) {
+      const bool upd = pend != 0 && done == 0 && mcopy == nullptr;
+      const bool ls_upd = upd && ls != 0;
+      for (int base = first; base < total; base += U * nthr) {
+        if (!(prefetched && base == first)) load(base);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int idx = base + u * nthr;
-        if (idx >= total) continue;
-        const int r = idx / nx, x = idx - r * nx;
-        const size_t i = row0 + idx;
-        if (ls_upd) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            if (retry) {
-              mi[u][c] = mbase[(size_t)c * N + i];
-            } else {
-              const T gt = g2[(size_t)c * N + i];
-              gi[u][c] = (double)gt;
-              mbase[(size_t)c * N + i] = mi[u][c];
-              const_cast<T*>(g)[(size_t)c * N + i] = gt;
-            }
-          }
+        for (int u = 0; u < U; ++u) {
+          const int idx = base + u * nthr;
+          if (idx < total) cell(idx, mi[u], gi[u], upd, ls_upd);
         }
-        if (upd) {
-          double mo[3];
-          cayley_step(mi[u], gi[u], tau, mo);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            m[(size_t)c * N + i] = mo[c];
-            sbuf[(size_t)c * N + i] = (T)(mo[c] - mi[u][c]);
-            mi[u][c] = mo[c];
-          }
-        }
-        if (mcopy != nullptr && done == 0) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) mcopy[(size_t)c * N + i] = mi[u][c];
-        }
-        if (msub != nullptr) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) mi[u][c] -= msub[(size_t)c * N + i];
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          smr[2 * ((size_t)(r * 3 + c) * RG + (x >> 1)) + (x & 1)] = (T)mi[u][c];
       }
-    };
-    // the first pass's cells were loaded before the wait (blocks other than 0)
-    int base = first;
-    if (prefetched) {
-      if (base < total) process(base);
-      base += U * nthr;
-    }
-    for (; base < total; base += U * nthr) {
-      load(base);
-      process(base);
     }
   }
   if (done != 0) return;
@@ -445,14 +509,14 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
   }
 }
 
-template <typename T, int VL>
+template <typename T, int VL, bool FUSE>
 __global__ void __launch_bounds__(kXwThreads)
 k_xf_w(double* __restrict__ m, const T* __restrict__ g, T* __restrict__ sbuf,
        const MinState* st, int nx, int ny, int nz, int R, cx<T>* __restrict__ out,
        const cx<T>* __restrict__ twx, const double* __restrict__ msub,
        double* __restrict__ mcopy, FinFuse fz) {
-  xf_w_body<T, VL>(m, g, sbuf, st, nx, ny, nz, R, out, twx, xcd_remap(blockIdx.x, gridDim.x),
-                   msub, mcopy, fz);
+  xf_w_body<T, VL, FUSE>(m, g, sbuf, st, nx, ny, nz, R, out, twx,
+                         xcd_remap(blockIdx.x, gridDim.x), msub, mcopy, fz);
 }
 
 // Body of the inverse x pass with the local terms for logical block L.
@@ -597,7 +661,7 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
 template <typename T, int VL>
 __device__ __forceinline__ void xf_desc(const BatchDesc& d, int block) {
   const FinFuse none{nullptr, nullptr, 0.0, 0.0, 0, 0};
-  xf_w_body<T, VL>(d.m, static_cast<const T*>(d.g), static_cast<T*>(d.s), d.st, d.nx, d.ny,
+  xf_w_body<T, VL, false>(d.m, static_cast<const T*>(d.g), static_cast<T*>(d.s), d.st, d.nx, d.ny,
                    d.nz, d.R, (cx<T>*)d.spec, (const cx<T>*)d.twx, block,
                    d.pass == 1 ? d.mref : nullptr, d.pass == 2 ? d.mref : nullptr, none);
 }
@@ -739,7 +803,7 @@ static void xf_wave(hipStream_t s, double* m, const T* g, T* sbuf, const MinStat
                     double* mcopy, const FinFuse& fz) {
   const size_t lds = (size_t)3 * R * wx_region<VL>() * sizeof(cx<T>);
   const int nb = nz * ((ny + R - 1) / R);
-  auto k = k_xf_w<T, VL>;
+  auto k = fz.st != nullptr ? k_xf_w<T, VL, true> : k_xf_w<T, VL, false>;
   set_lds(k, lds);
   hipLaunchKernelGGL(k, dim3(nb), dim3(192 * R), lds, s, m, g, sbuf, st, nx, ny, nz, R,
                      (cx<T>*)out, (const cx<T>*)twx, msub, mcopy, fz);
