@@ -1390,6 +1390,7 @@ int ensure_ls(mm_ctx* c, Sample& s) {
 // Minimiser state reset of a run: BB state, stop rule, step choice and
 // (when on) the line search with the sample's buffers.
 void reset_run(mm_ctx* c, hipStream_t st, Sample& s, double tol, long long max_iter) {
+  s.fin_pending = false;   // a reset state drops any pending finish
   launch_reset_state(st, s.st, tau0_of(c, s), tol, max_iter, stall_of(c, s), 0, s.H, c->bb_switch,
                      c->ls.on ? &c->ls : nullptr, s.ls_mbase, s.ls_g2);
 }
@@ -1676,6 +1677,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   s.evals_total = s.iters_total = 0;
   if (s.has_mat)
     launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
+  s.fin_pending = false;   // a reset state drops any pending finish
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1711,6 +1713,7 @@ int mm_set_material(mm_ctx* c, int sample, double Ms, double A, double Ku, const
   s.ref_age = kRefStale;   // the reference field scales with Ms
   ++s.mat_version;         // material constants are baked into captured launches
   launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
+  s.fin_pending = false;   // a reset state drops any pending finish
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1724,6 +1727,7 @@ int mm_set_field(mm_ctx* c, int sample, const double* H) {
   for (int q = 0; q < 3; ++q) s.H[q] = H[q];
   if (s.has_mat)
     launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
+  s.fin_pending = false;   // a reset state drops any pending finish
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
@@ -1733,6 +1737,7 @@ int mm_reset(mm_ctx* c, int sample) {
   if (rc != MM_OK) return rc;
   Sample& s = c->smp[sample];
   launch_reset_state(c->stream, s.st, tau0_of(c, s), 0.0, 0, 0, 1, s.H, c->bb_switch);
+  s.fin_pending = false;   // a reset state drops any pending finish
   HIPCHK(c, hipGetLastError());
   return MM_OK;
 }
