@@ -28,6 +28,13 @@
 
 namespace mmk {
 
+// The stages transpose through a full wave buffer of the wave FFT (one
+// exchange per pass), not the half buffer (half the LDS, twice the
+// exchanges): LDS does not limit these kernels, registers do, and the full
+// buffer also takes fewer of those (FP64, 256 points: y3_fwd 132 against
+// 160 VGPRs, z3 170 against 172).
+constexpr bool k3dHalf = false;
+
 constexpr int kY3Waves = 4;   // (kx, z) planes per block of the y passes
 constexpr int kZ3Waves = 4;   // (kx, ky) pencils per block of the z pass
 
@@ -222,7 +229,7 @@ static_assert(kY3Waves == kZ3Waves, "the 3-D stages share one block size");
 
 template <typename T, int VL>
 __device__ __forceinline__ void w3_item(int stage, const BatchDesc& d, int L) {
-  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  constexpr bool HALF = k3dHalf;
   const int nzb = (d.nz + kY3Waves - 1) / kY3Waves;
   if (stage < 0)
     y3_fwd_body<T, VL, HALF>((const cx<T>*)d.spec, (cx<T>*)d.B, d.nz, d.ny, nzb,
@@ -262,7 +269,7 @@ static void set_lds(K kernel, size_t bytes) {
 template <typename T, int VL>
 static void y3_dispatch(hipStream_t s, void* A, void* B, int nz, int ny, int M, int dir,
                         const void* twy, const int* done) {
-  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  constexpr bool HALF = k3dHalf;
   const size_t lds = (size_t)kY3Waves * wfft_buf<VL, HALF>() * sizeof(cx<T>);
   const int nzb = (nz + kY3Waves - 1) / kY3Waves;
   const dim3 grid((unsigned)((M + 1) * nzb));
@@ -293,7 +300,7 @@ void launch_y3(hipStream_t s, void* A, void* B, int nz, int ny, int Py, int M, i
 template <typename T, int VL>
 static void z3_dispatch(hipStream_t s, void* B, int nz, int Py, int M, const T* T3, int rstride,
                         T scale, const void* twz, const int* done) {
-  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  constexpr bool HALF = k3dHalf;
   const size_t lds = (size_t)kZ3Waves * wfft_buf<VL, HALF>() * sizeof(cx<T>);
   // Py is a multiple of kZ3Waves, so every wave of the grid owns a pencil
   const dim3 grid((unsigned)((long long)(M + 1) * Py / kZ3Waves));
@@ -319,7 +326,7 @@ int z3_blocks(int Py, int M) { return (M + 1) * (Py / kZ3Waves); }
 
 template <typename T, int VL>
 static size_t w3_lds() {
-  constexpr bool HALF = sizeof(T) == 8 && VL >= 4;
+  constexpr bool HALF = k3dHalf;
   return (size_t)kY3Waves * wfft_buf<VL, HALF>() * sizeof(cx<T>);
 }
 
