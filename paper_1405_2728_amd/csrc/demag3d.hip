@@ -213,8 +213,10 @@ __device__ __forceinline__ void z3_body(cx<T>* __restrict__ B, int nz, int Py,
   }
 }
 
+// FP64 up to 256 points: compiled for 3 resident waves per SIMD (168
+// VGPRs, no spill; 170 and 2 waves otherwise)
 template <typename T, int VL, bool HALF>
-__global__ void __launch_bounds__(64 * kZ3Waves)
+__global__ void __launch_bounds__(64 * kZ3Waves, (sizeof(T) == 8 && VL <= 4 ? 3 : 1))
 k_z3(cx<T>* __restrict__ B, int nz, int Py, const T* __restrict__ T3, int rstride, T scale,
      const cx<T>* __restrict__ twz, const int* __restrict__ done) {
   z3_body<T, VL, HALF>(B, nz, Py, T3, rstride, scale, twz, done,
