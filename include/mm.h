@@ -324,7 +324,10 @@ int mm_mean(mm_ctx* ctx, int sample, const double* m, double* mavg);
  * step after issuing their first loads; every poll interval still ends
  * with a finish kernel; not with the line search or a two-stage
  * reduction (more than 2048 per-block sums); 0: a finish kernel after
- * every iteration; results are the same either way).
+ * every iteration; results are the same either way), "fin_spin" (default
+ * 2^22: polls of the published step before a waiting block gives up, writes
+ * nothing and flags the run, which then fails with MM_ESTATE; an integer in
+ * [0, 2^30], small values for testing that path).
  * Unknown keys or values give MM_EINVAL. */
 int mm_set_option(mm_ctx* ctx, const char* key, double value);
 

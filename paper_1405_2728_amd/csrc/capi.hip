@@ -137,6 +137,7 @@ struct mm_ctx {
                                 // equal transform lengths
   int fused_finish = 1;         // single-sample runs: the next forward x pass takes each
                                 // iteration's finish over (0: a finish kernel each)
+  int fin_spin = kFinSpin;      // polls before a block waiting for that decision gives up
   // auxiliary streams (default priority) and fork/join events of the
   // batched passes, made on first use
   std::vector<hipStream_t> aux;
@@ -622,7 +623,7 @@ void enqueue_reference(mm_ctx* c, Sample& s, const double* m, const MinState* ms
 void enqueue_eval(mm_ctx* c, Sample& s, const double* m, const EvalOut& o) {
   if (o.fuse_q <= 0) flush_finish(c, s);
   hipStream_t st = c->stream;
-  FinFuse fz{nullptr, nullptr, s.Ms, s.V, s.nb3, 0};
+  FinFuse fz{nullptr, nullptr, s.Ms, s.V, s.nb3, 0, c->fin_spin};
   if (o.fuse_q >= 0) {
     fz.st = s.st;
     fz.par = o.fuse_q & 1;
@@ -2099,6 +2100,10 @@ int mm_set_option(mm_ctx* c, const char* key, double value) {
     c->persistent = value != 0.0;
   } else if (!std::strcmp(key, "fused_finish")) {
     c->fused_finish = value != 0.0;
+  } else if (!std::strcmp(key, "fin_spin")) {
+    if (!(value >= 0.0 && value <= (double)(1 << 30)) || value != std::floor(value))
+      return fail(c, MM_EINVAL, "fin_spin is an integer in [0, 2^30]");
+    c->fin_spin = (int)value;
   } else if (!std::strcmp(key, "autotune")) {
     c->autotune = value != 0.0;
   } else if (!std::strcmp(key, "yz_variant")) {

@@ -237,7 +237,7 @@ __device__ __forceinline__ double fin_wait(const FinFuse& fz) {
   if (threadIdx.x == 0) {
     unsigned long long* slot = &fz.st->fin_slot[fz.par];
     unsigned long long b = kFinSent;
-    for (int n = 0; n < kFinSpin; ++n) {
+    for (int n = 0; n < fz.spin; ++n) {
       b = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (b != kFinSent) break;
       __builtin_amdgcn_s_sleep(2);
@@ -660,7 +660,7 @@ k_xil_w(const cx<T>* __restrict__ in, LocalArgs a, int R, double* __restrict__ H
 // Logical block `block` of sample d's forward x pass.
 template <typename T, int VL>
 __device__ __forceinline__ void xf_desc(const BatchDesc& d, int block) {
-  const FinFuse none{nullptr, nullptr, 0.0, 0.0, 0, 0};
+  const FinFuse none{nullptr, nullptr, 0.0, 0.0, 0, 0, 0};
   xf_w_body<T, VL, false>(d.m, static_cast<const T*>(d.g), static_cast<T*>(d.s), d.st, d.nx, d.ny,
                    d.nz, d.R, (cx<T>*)d.spec, (const cx<T>*)d.twx, block,
                    d.pass == 1 ? d.mref : nullptr, d.pass == 2 ? d.mref : nullptr, none);
@@ -830,7 +830,7 @@ template <typename T>
 void launch_xf(hipStream_t s, double* m, const T* g, T* sbuf, const MinState* st, int nx, int ny,
                int nz, int Px, int R, void* out, const void* twx, const double* msub,
                double* mcopy, const FinFuse* fzp) {
-  const FinFuse fz = fzp != nullptr ? *fzp : FinFuse{nullptr, nullptr, 0.0, 0.0, 0, 0};
+  const FinFuse fz = fzp != nullptr ? *fzp : FinFuse{nullptr, nullptr, 0.0, 0.0, 0, 0, 0};
   const int M = Px / 2;
   switch (M) {
     case 64: xf_wave<T, 1>(s, m, g, sbuf, st, nx, ny, nz, R, out, twx, msub, mcopy, fz); return;

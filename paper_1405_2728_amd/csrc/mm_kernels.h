@@ -86,13 +86,14 @@ struct FinFuse {
   const double* partials;
   double Ms, V;
   int nb, par;
+  int spin;   // polls of the slot before a waiting block gives up
 };
 // published words: a signalling NaN (never an arithmetic result) until the
 // decision, -1 stop, -2 no update, else the step tau > 0
 constexpr unsigned long long kFinSent = 0x7FF4000000000001ull;
 constexpr double kFinStop = -1.0, kFinNoUpdate = -2.0;
-// polls of the slot before a block gives up (fin_err), with a short sleep
-// between them: far beyond any finish (microseconds)
+// default polls of the slot before a block gives up (fin_err), with a short
+// sleep between them: far beyond any finish (microseconds)
 constexpr int kFinSpin = 1 << 22;
 
 // Conjugate-gradient state of an adjoint solve, resident in device memory.

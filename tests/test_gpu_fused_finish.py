@@ -7,7 +7,9 @@ arithmetic is the finish kernel's, so runs with the option on and off must
 agree bitwise: fixed iteration counts, runs that stop inside a poll
 interval, device-driven sweeps (field changes leave no update pending),
 several rows per block (idle threads in the reduction) and replays of a
-captured graph."""
+captured graph.  The waiting blocks' poll is bounded; with the bound set to
+zero from the host ("fin_spin") they give up at once, and the run must fail
+with MM_ESTATE instead of returning a result."""
 
 import sys
 
@@ -129,3 +131,33 @@ def test_sweep_equal(torch_cuda, prec):
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])
     assert np.array_equal(a[3], b[3])
+
+
+def test_give_up_is_reported(torch_cuda):
+    """Every waiting block gives up at once (no poll): the run reports
+    MM_ESTATE; after a reset the context runs normally again."""
+    torch = torch_cuda
+    from paper_1405_2728_amd import Context
+    from paper_1405_2728_amd.api import MMError
+    say("case give-up path")
+    n = (200, 100, 2)
+    rng = np.random.default_rng(5)
+    m0 = synth.uniform_with_noise(synth.tilted(30.0), *n, 0.3, rng)
+    ctx = Context("fp64")
+    ctx.set_option("poll_every", 16)
+    ctx.set_geometry(0, *n, 5e-9, 5e-9, 5e-9)
+    ctx.set_material(0, 8e5, 1.3e-11, 500.0, (1.0, 0.0, 0.0))
+    ctx.set_field(0, (-4e3, 1.5e3, 0.0))
+    m = torch.tensor(m0, device="cuda")
+    ctx.set_option("fin_spin", 0)
+    with pytest.raises(MMError) as e:
+        ctx.minimize_to_tol(0, m, tol=0.0, max_iter=40)
+    say("  error", e.value)
+    assert e.value.code == -5 and "gave up" in str(e.value)
+    ctx.set_option("fin_spin", 1 << 22)
+    m.copy_(torch.tensor(m0, device="cuda"))
+    r = ctx.minimize_to_tol(0, m, tol=0.0, max_iter=40)
+    ctx.close()
+    ref = relax(torch, "fp64", n, False, 0.0, 40)
+    assert r["iters"] == 40
+    assert np.array_equal(m.cpu().numpy(), ref[1])

@@ -112,6 +112,10 @@ def test_argument_validation_without_gpu(lib):
         assert lib.mm_set_option(h, b"persistent", 1.0) == 0
         assert lib.mm_set_option(h, b"fused_finish", 0.0) == 0
         assert lib.mm_set_option(h, b"fused_finish", 1.0) == 0
+        assert lib.mm_set_option(h, b"fin_spin", -1.0) == -1
+        assert lib.mm_set_option(h, b"fin_spin", 2.5) == -1
+        assert lib.mm_set_option(h, b"fin_spin", 0.0) == 0
+        assert lib.mm_set_option(h, b"fin_spin", 4194304.0) == 0
         assert lib.mm_set_option(h, b"batch_rebuild", 1.0) == -1
         assert lib.mm_set_option(h, b"batch_rebuild", 0.0) == 0
         assert lib.mm_set_option(h, b"batch_rebuild", 0.75) == 0
