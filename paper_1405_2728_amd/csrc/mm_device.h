@@ -296,25 +296,48 @@ __device__ void fft_lds(cx<T>* buf, int n, int nseq, int stride, const cx<T>* __
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic block reductions (fixed order: wave shuffle tree, then the
-// waves' partials in index order).
+// Deterministic block reductions (fixed order: a fixed cross-lane pattern
+// within each wave, then the waves' partials in index order).
 // ---------------------------------------------------------------------------
+// The other lane's value of v through a DPP move (both 32-bit halves); lanes
+// whose source is outside their row, or rows outside ROWS, get `old`.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Wave total in lane 63: an inclusive scan within each row of 16 lanes
+// (row_shr 1, 2, 4, 8: lane 15 of a row holds the row's total), then row 0's
+// total into row 1 and row 2's into row 3 (row_bcast 15), then lane 31's
+// into rows 2 and 3 (row_bcast 31).  No LDS traffic.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  v += dpp_f64<0x111>(0.0, v);
+  v += dpp_f64<0x112>(0.0, v);
+  v += dpp_f64<0x114>(0.0, v);
+  v += dpp_f64<0x118>(0.0, v);
+  v += dpp_f64<0x142, 0xa>(0.0, v);
+  v += dpp_f64<0x143, 0xc>(0.0, v);
   return v;
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  v = fmax(v, dpp_f64<0x111>(v, v));
+  v = fmax(v, dpp_f64<0x112>(v, v));
+  v = fmax(v, dpp_f64<0x114>(v, v));
+  v = fmax(v, dpp_f64<0x118>(v, v));
+  v = fmax(v, dpp_f64<0x142, 0xa>(v, v));
+  v = fmax(v, dpp_f64<0x143, 0xc>(v, v));
   return v;
 }
 
 // Reduce NV values per thread across the block; result valid in thread 0.
-// MAXT is the kernel's launch bound (blockDim.x <= MAXT); scratch holds
-// NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs sum.  Each wave
-// reduces in registers; then lane i of the first wave combines value i over
-// the waves (in wave order, so the result does not depend on timing).
+// MAXT is the kernel's launch bound (blockDim.x <= MAXT, whole waves);
+// scratch holds NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs
+// sum.  Each wave reduces in registers (total in lane 63); then lane i of
+// the first wave combines value i over the waves (in wave order, so the
+// result does not depend on timing).
 template <int MAXT, int NV, int NS>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV],
                                              double (&scratch)[NS]) {
@@ -324,7 +347,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
   const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = is_max[i] ? wave_max(v[i]) : wave_sum(v[i]);
-  if (lane == 0) {
+  if (lane == 63) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) scratch[i * nw + wid] = v[i];
   }
