@@ -640,11 +640,8 @@ __device__ __forceinline__ void xil_w_body(const cx<T>* __restrict__ in, LocalAr
   }
   bool is_max[kNPartial];
   for (int q = 0; q < kNPartial; ++q) is_max[q] = q == kPartMax;
-  block_reduce<kXwThreads>(part, is_max, scratch);
-  if (partials != nullptr && tid == 0) {
-#pragma unroll
-    for (int v = 0; v < kNPartial; ++v) partials[(size_t)L * kNPartial + v] = part[v];
-  }
+  if (partials != nullptr)
+    block_reduce_store<kXwThreads>(part, is_max, scratch, partials + (size_t)L * kNPartial);
 }
 
 template <typename T, int VL>

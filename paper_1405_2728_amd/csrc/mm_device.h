@@ -332,15 +332,15 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Reduce NV values per thread across the block; result valid in thread 0.
-// MAXT is the kernel's launch bound (blockDim.x <= MAXT, whole waves);
-// scratch holds NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs
-// sum.  Each wave reduces in registers (total in lane 63); then lane i of
-// the first wave combines value i over the waves (in wave order, so the
-// result does not depend on timing).
+// Reduce NV values per thread across the block.  MAXT is the kernel's
+// launch bound (blockDim.x <= MAXT, whole waves); scratch holds
+// NV * MAXT / 64 doubles of LDS.  is_max[i] selects max vs sum.  Each wave
+// reduces in registers (total in lane 63); then lane i of the first wave
+// combines value i over the waves (in wave order, so the result does not
+// depend on timing) and returns it (threads i < NV; others return 0).
 template <int MAXT, int NV, int NS>
-__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV],
-                                             double (&scratch)[NS]) {
+__device__ __forceinline__ double block_combine(double (&v)[NV], const bool (&is_max)[NV],
+                                                double (&scratch)[NS]) {
   static_assert(NS >= NV * (MAXT / 64), "reduction scratch smaller than one slot per wave");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -352,20 +352,39 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
     for (int i = 0; i < NV; ++i) scratch[i * nw + wid] = v[i];
   }
   __syncthreads();
+  double a = 0.0;
   if (threadIdx.x < NV) {
     const int i = threadIdx.x;
     bool mx = false;
 #pragma unroll
     for (int q = 0; q < NV; ++q) mx = q == i ? is_max[q] : mx;
-    double a = scratch[i * nw];
+    a = scratch[i * nw];
     for (int w = 1; w < nw; ++w) a = mx ? fmax(a, scratch[i * nw + w]) : a + scratch[i * nw + w];
-    scratch[i * nw] = a;
   }
+  return a;
+}
+
+// The block's results in v[] of thread 0.
+template <int MAXT, int NV, int NS>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV],
+                                             double (&scratch)[NS]) {
+  const double a = block_combine<MAXT>(v, is_max, scratch);
+  const int nw = (blockDim.x + 63) >> 6;
+  if (threadIdx.x < NV) scratch[threadIdx.x * nw] = a;
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = scratch[i * nw];
   }
+}
+
+// The block's results stored to out[0 .. NV) by threads 0 .. NV-1 (one
+// barrier fewer than block_reduce; scratch is reused only after another).
+template <int MAXT, int NV, int NS>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (&is_max)[NV],
+                                                   double (&scratch)[NS], double* out) {
+  const double a = block_combine<MAXT>(v, is_max, scratch);
+  if (threadIdx.x < NV) out[threadIdx.x] = a;
 }
 
 }  // namespace mmk
