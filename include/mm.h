@@ -80,7 +80,7 @@ enum mm_status {
   MM_EHIP = -3,           /* HIP runtime error                             */
   MM_ENONFINITE = -4,     /* non-finite torque or energy encountered       */
   MM_ESTATE = -5,         /* call out of order (e.g. no geometry yet)      */
-  MM_EUNSUPPORTED = -6    /* grid shape not supported by this build        */
+  MM_EUNSUPPORTED = -6    /* grid shape not supported by the kernels      */
 };
 
 /* Per-iteration information (host struct). torque is max|g|/Ms before the
@@ -115,7 +115,7 @@ void mm_destroy(mm_ctx* ctx);
  * device (once per geometry) and allocates the sample's work buffers.
  * Resets the minimiser state.  The demag path follows the "demag_path"
  * option in force at this call.  MM_EUNSUPPORTED if the shape exceeds what
- * this build's kernels handle (see mm_supported); MM_ENOMEM if the device
+ * the library's kernels handle (see mm_supported); MM_ENOMEM if the device
  * cannot hold the set-up temporaries (full 3-D path: about
  * 192 (Px/2+1) Py Pz bytes, Px, Py, Pz the padded lengths). */
 int mm_set_geometry(mm_ctx* ctx, int sample, int nx, int ny, int nz,
@@ -344,7 +344,7 @@ int mm_yz_variant(mm_ctx* ctx, int sample, int* var);
  * effective-field evaluations and updates (host int64_t outputs). */
 int mm_counters(mm_ctx* ctx, int sample, int64_t* heff_evals, int64_t* iters);
 
-/* Whether this build's kernels handle a grid (1) or not (0) with the
+/* Whether the library's kernels handle a grid (1) or not (0) with the
  * automatic demag path (and the default "mixed_radix" padding): nx <= 2048
  * (the fused x passes hold a row's three components, 3 Px/2 complex values,
  * in one block);

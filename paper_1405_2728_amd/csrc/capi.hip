@@ -1580,7 +1580,7 @@ int mm_set_geometry(mm_ctx* c, int sample, int nx, int ny, int nz, double dx, do
   const bool mr = c->mixed_radix != 0;
   const int path = choose_path(c->prec, c->path_pref, nx, ny, nz, mr);
   if (path == PATH_NONE)
-    return fail(c, MM_EUNSUPPORTED, "grid shape not supported by this build's kernels");
+    return fail(c, MM_EUNSUPPORTED, "grid shape not supported by the library's kernels");
   (void)hipStreamSynchronize(c->stream);
   Sample& s = c->smp[sample];
   const double Ms = s.Ms, A = s.A, Ku = s.Ku;

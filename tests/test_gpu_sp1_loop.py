@@ -6,8 +6,8 @@ tol 1e-6 (paper Sec. 4: the hysteresis loop of Fig. 1 / Fig. 3(c), the
 mesh of the Tab. 1 comparison).
 
 The method finds a local minimiser from the previous field's state, and
-near a switch rounding can select another metastable state (survey reading
-of "several correct results"), so the comparison is:
+near a switch rounding can select another metastable state (several
+results are correct there), so the comparison is:
 * the coercive field of each branch (first field where <m>.h changes sign)
   lies within one field step of the oracle's;
 * before the first switch the states are determined: <m> agrees with the

@@ -9,7 +9,7 @@ then the one-block finish (stop rule and step of eq. (12)) -- the kernels
 `bench.py` times.  The iterates come from runs to tolerance 0 with
 max_iter = k (the device-driven loop), not from single steps.
 
-Bounds (survey: the first 10 tau_k and m_k agree to 1e-8 relative):
+Bounds (the first 10 tau_k and m_k agree to 1e-8 relative):
 * near-uniform starts: m_k (max abs over cells and components), tau_k,
   torque_k and U(m_k) within 1e-8 relative;
 * random start: the first BB steps rotate cells by up to ~pi and amplify
