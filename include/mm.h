@@ -185,6 +185,38 @@ int mm_minimize_step(mm_ctx* ctx, int sample, double* m, mm_step_info* info);
 int mm_minimize_to_tol(mm_ctx* ctx, int sample, double* m, double tol,
                        int64_t max_iter, mm_min_result* out);
 
+/* Continue the run held in the context (after mm_minimize_step calls, a run
+ * that ended, or mm_state_load) on m (device [3][N], updated in place) until
+ * max|g|/Ms < tol or the run's update count k reaches max_iter (a total over
+ * the whole run, not a number of further updates).  Keeps k, tau, the BB
+ * sums and the stored g and s (eq. (12)) and, in MM_MIXED, the reference of
+ * the defect correction, so that the iterates are those of one
+ * uninterrupted run with these limits.  Where the run ended at its last
+ * evaluation (stop rule or max_iter), that evaluation's decision is taken
+ * again with the new limits: stop, or the step of eq. (12) from the
+ * recorded sums.  m must hold the state's m_k (the caller owns it: restore
+ * it with the checkpoint).  out receives the whole run's counts.  Returns as
+ * mm_minimize_to_tol; MM_EINVAL while the line search is on. */
+int mm_minimize_continue(mm_ctx* ctx, int sample, double* m, double tol,
+                         int64_t max_iter, mm_min_result* out);
+
+/* Checkpoint of a relaxation in progress (the minimiser of Sec. 2 between
+ * two iterations): the run's scalars (k, tau, the BB sums of eq. (12),
+ * torque, energy, limits, the field), the stored g_k and s_k (the
+ * context's transform type) and, in MM_MIXED with the defect correction,
+ * the reference m_ref and H_d(m_ref) with its age.  m is not part of it
+ * (the caller owns m).  mm_state_bytes gives the size (host *bytes);
+ * mm_state_save writes it to host memory (host, at least that many bytes;
+ * synchronises; runs a pending finish first); mm_state_load restores it
+ * into a sample of the same precision, grid and correction setting (else
+ * MM_EINVAL; also for a short or foreign buffer), replacing the sample's run
+ * state and its field.  A restored state continues with mm_minimize_step or
+ * mm_minimize_continue bit for bit as the saved run would have.  Both
+ * return MM_EINVAL while the line search is on. */
+int mm_state_bytes(mm_ctx* ctx, int sample, int64_t* bytes);
+int mm_state_save(mm_ctx* ctx, int sample, void* host, int64_t bytes);
+int mm_state_load(mm_ctx* ctx, int sample, const void* host, int64_t bytes);
+
 /* Hysteresis sweep (Sec. 4) of every sample: m is a host array of
  * n_samples device pointers ([3][N_s] double each, updated in place);
  * H is host double[n_samples][n_fields][3] (A/m).  For each field the

@@ -55,6 +55,11 @@ SIGNATURES = {
     "mm_energy_grads": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(C.c_double)]),
     "mm_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
+    "mm_minimize_continue": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_int64,
+                                       C.POINTER(MinResult)]),
+    "mm_state_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
+    "mm_state_save": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
+    "mm_state_load": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
     "mm_last_step": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(StepInfo)]),
     "mm_counters": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mm_rows_per_block": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),

@@ -171,6 +171,31 @@ class Context:
         return {"status": rc, "converged": rc == 0, "iters": r.iters,
                 "heff_evals": r.heff_evals, "torque": r.torque, "energy": r.energy}
 
+    def minimize_continue(self, sample, m, tol=1e-6, max_iter=100000):
+        """Continue the context's run on m (mm_minimize_continue); max_iter
+        caps the run's total update count."""
+        r = _lib.MinResult()
+        rc = self._check(self._lib.mm_minimize_continue(self._h, sample,
+                                                        _dev_ptr(m, self._n3(sample), "m"),
+                                                        float(tol), int(max_iter), C.byref(r)),
+                         allow_positive=True)
+        return {"status": rc, "converged": rc == 0, "iters": r.iters,
+                "heff_evals": r.heff_evals, "torque": r.torque, "energy": r.energy}
+
+    def state_save(self, sample):
+        """Checkpoint of the sample's run (mm_state_save) as bytes; m is not
+        part of it."""
+        n = C.c_int64()
+        self._check(self._lib.mm_state_bytes(self._h, sample, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self._lib.mm_state_save(self._h, sample, buf, n.value))
+        return buf.raw
+
+    def state_load(self, sample, blob):
+        """Restore a checkpoint written by state_save (mm_state_load)."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._check(self._lib.mm_state_load(self._h, sample, buf, len(blob)))
+
     def last_step(self, sample):
         """tau of the most recent update, torque and energy of the most
         recent evaluation and its index k (mm_last_step)."""

@@ -1396,20 +1396,30 @@ void reset_run(mm_ctx* c, hipStream_t st, Sample& s, double tol, long long max_i
                      c->ls.on ? &c->ls : nullptr, s.ls_mbase, s.ls_g2);
 }
 
-int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
-  int lrc = ensure_ls(c, s);
-  if (lrc != MM_OK) return lrc;
-  reset_run(c, c->stream, s, tol, (long long)max_iter);
-  s.ref_age = kRefStale;
+// Poll loop of a run whose device state is set: batches of poll_every
+// iterations until the state ends the run.  left bounds the evaluations
+// enqueued (launches beyond the end would only read the stop flag and
+// return); k0 and e0 are the state's update and evaluation counts when the
+// loop starts (the context's totals count what the loop adds).
+int run_loop(mm_ctx* c, Sample& s, double* m, long long left, long long k0, long long e0,
+             mm_min_result* out) {
   // full batches after the first replay a captured graph (use_graph on a
   // non-null stream, kernels not being timed); the first batch runs eagerly
   const bool graph = c->use_graph && c->stream != nullptr && c->prof == 0;
-  // a run evaluates at most max_iter + 1 times: enqueue no iteration beyond
-  // that (such launches would only read the stop flag and return)
-  long long left = (long long)max_iter + 1;
+  // A captured batch starts with the reference pass of the defect
+  // correction; with a reference younger than poll_every (a continued run)
+  // the first batch ends where it falls due, so that the references come at
+  // the iterations of an uninterrupted run
+  long long first = c->poll_every;
+  if (use_ref(c, s) && s.ref_age >= 0 && s.ref_age < c->poll_every) first = c->poll_every - s.ref_age;
+  long long evals_before = e0;
   for (int nbatch = 0;; ++nbatch) {
-    const long long batch = left < 1 ? 1 : (left < c->poll_every ? left : c->poll_every);
-    if (graph && nbatch > 0 && batch == c->poll_every) {
+    const long long cap = nbatch == 0 ? first : c->poll_every;
+    const long long batch = left < 1 ? 1 : (left < cap ? left : cap);
+    const bool replay = graph && nbatch > 0 && batch == c->poll_every;
+    // reference age before the batch (a captured batch starts with the pass)
+    const long long age_before = replay ? c->poll_every : s.ref_age;
+    if (replay) {
       int rc = ensure_iter_graph(c, s, m);
       if (rc != MM_OK) return rc;
       HIPCHK(c, hipGraphLaunch(s.it_graph, c->stream));
@@ -1425,15 +1435,28 @@ int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm
     prof_collect(c);
     if (s.st_host->fin_err != 0)
       return fail(c, MM_ESTATE, "a forward x pass gave up waiting for the finish decision");
-    if (s.st_host->done != 0) break;
+    if (s.st_host->done != 0) {
+      // iterations enqueued after the run ended did nothing: the reference
+      // age counts the evaluations that ran (a continued run needs it)
+      if (use_ref(c, s)) {
+        long long age = age_before;
+        for (long long q = 0; q < s.st_host->evals - evals_before; ++q) {
+          if (age >= c->poll_every) age = 0;
+          ++age;
+        }
+        s.ref_age = age;
+      }
+      break;
+    }
+    evals_before = s.st_host->evals;
     // the evaluation that reaches max_iter ends the run on the device; a
     // state that still runs well after it would keep the host polling
     if (left < -(long long)c->poll_every)
       return fail(c, MM_ESTATE, "the device state did not end the run at max_iter");
   }
   const MinState& h = *s.st_host;
-  s.evals_total += h.evals;
-  s.iters_total += h.k;
+  s.evals_total += h.evals - e0;
+  s.iters_total += h.k - k0;
   if (out) {
     out->status = status_of(h.done);
     out->iters = h.k;
@@ -1443,6 +1466,15 @@ int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm
   }
   if (h.done == -1) return fail(c, MM_ENONFINITE, "non-finite torque or energy");
   return status_of(h.done);
+}
+
+int run_to_tol(mm_ctx* c, Sample& s, double* m, double tol, int64_t max_iter, mm_min_result* out) {
+  int lrc = ensure_ls(c, s);
+  if (lrc != MM_OK) return lrc;
+  reset_run(c, c->stream, s, tol, (long long)max_iter);
+  s.ref_age = kRefStale;
+  // a run evaluates at most max_iter + 1 times
+  return run_loop(c, s, m, (long long)max_iter + 1, 0, 0, out);
 }
 
 // Allocate the derivative workspace of a sample on first use.
@@ -1857,6 +1889,192 @@ int mm_minimize_to_tol(mm_ctx* c, int sample, double* m, double tol, int64_t max
   if (rc != MM_OK) return rc;
   if (!m || !(tol >= 0) || max_iter < 0) return fail(c, MM_EINVAL, "bad argument");
   return run_to_tol(c, c->smp[sample], m, tol, max_iter, out);
+}
+
+int mm_minimize_continue(mm_ctx* c, int sample, double* m, double tol, int64_t max_iter,
+                         mm_min_result* out) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!m || !(tol >= 0) || max_iter < 0) return fail(c, MM_EINVAL, "bad argument");
+  if (c->ls.on) return fail(c, MM_EINVAL, "a line-search run is not continued");
+  Sample& s = c->smp[sample];
+  rc = read_state(c, s);   // also runs a pending finish
+  if (rc != MM_OK) return rc;
+  if (s.st_host->done == -1) return fail(c, MM_ENONFINITE, "the run ended on a non-finite state");
+  const long long k0 = s.st_host->k, e0 = s.st_host->evals;
+  launch_continue_state(c->stream, s.st, tol, (long long)max_iter, stall_of(c, s));
+  HIPCHK(c, hipGetLastError());
+  // at most max_iter - k0 + 1 evaluations remain (k0 + 1 where a step was
+  // just decided; the device state ends the run in either case)
+  const long long left = (long long)max_iter - k0 + 1;
+  return run_loop(c, s, m, left < 1 ? 1 : left, k0, e0, out);
+}
+
+// ---- checkpoint of a run ----------------------------------------------------
+namespace {
+
+// The run fields of MinState (no pointers, sweep or line-search bookkeeping).
+struct CkptRun {
+  double tau, torque, energy, eterm[4], ss, sy, yy, best_torque, tol, tau0;
+  long long k, best_k, evals, max_iter, stall_iters;
+  int done, mode;
+  double last_tau;
+  long long last_k;
+  int pending, pad;
+  double H[3];
+  double bb_switch;
+};
+
+struct CkptHeader {
+  char magic[8];
+  int32_t version, prec, nx, ny, nz, gs, has_ref, pad;
+  int64_t ref_age, bytes;
+  CkptRun run;
+};
+
+constexpr char kCkptMagic[8] = {'M', 'M', 'B', 'B', 'C', 'K', 'P', 'T'};
+
+int64_t ckpt_bytes(const mm_ctx* c, const Sample& s) {
+  const int64_t n3 = 3LL * s.N;
+  int64_t b = (int64_t)sizeof(CkptHeader) + 2 * n3 * (int64_t)gs_bytes(c);
+  if (use_ref(c, s)) b += 2 * n3 * (int64_t)sizeof(double);
+  return b;
+}
+
+}  // namespace
+
+int mm_state_bytes(mm_ctx* c, int sample, int64_t* bytes) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!bytes) return fail(c, MM_EINVAL, "null pointer");
+  *bytes = ckpt_bytes(c, c->smp[sample]);
+  return MM_OK;
+}
+
+int mm_state_save(mm_ctx* c, int sample, void* host, int64_t bytes) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!host) return fail(c, MM_EINVAL, "null buffer");
+  if (c->ls.on) return fail(c, MM_EINVAL, "a line-search run is not checkpointed");
+  Sample& s = c->smp[sample];
+  const int64_t need = ckpt_bytes(c, s);
+  if (bytes < need)
+    return fail(c, MM_EINVAL, "checkpoint buffer of " + std::to_string(bytes) + " bytes; " +
+                                  std::to_string(need) + " needed");
+  rc = read_state(c, s);   // also runs a pending finish
+  if (rc != MM_OK) return rc;
+  const MinState& h = *s.st_host;
+  CkptHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, kCkptMagic, sizeof(kCkptMagic));
+  hd.version = 1;
+  hd.prec = c->prec;
+  hd.nx = s.nx;
+  hd.ny = s.ny;
+  hd.nz = s.nz;
+  hd.gs = (int32_t)gs_bytes(c);
+  hd.has_ref = use_ref(c, s) ? 1 : 0;
+  hd.ref_age = s.ref_age;
+  hd.bytes = need;
+  CkptRun& r = hd.run;
+  r.tau = h.tau;
+  r.torque = h.torque;
+  r.energy = h.energy;
+  for (int q = 0; q < 4; ++q) r.eterm[q] = h.eterm[q];
+  r.ss = h.ss;
+  r.sy = h.sy;
+  r.yy = h.yy;
+  r.best_torque = h.best_torque;
+  r.tol = h.tol;
+  r.tau0 = h.tau0;
+  r.k = h.k;
+  r.best_k = h.best_k;
+  r.evals = h.evals;
+  r.max_iter = h.max_iter;
+  r.stall_iters = h.stall_iters;
+  r.done = h.done;
+  r.mode = h.mode;
+  r.last_tau = h.last_tau;
+  r.last_k = h.last_k;
+  r.pending = h.pending;
+  for (int q = 0; q < 3; ++q) r.H[q] = h.H[q];
+  r.bb_switch = h.bb_switch;
+  unsigned char* p = static_cast<unsigned char*>(host);
+  std::memcpy(p, &hd, sizeof(hd));
+  p += sizeof(hd);
+  const size_t gsb = 3ull * s.N * gs_bytes(c), db = 3ull * s.N * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(p, s.g, gsb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(p + gsb, s.s, gsb, hipMemcpyDeviceToHost, c->stream));
+  if (hd.has_ref) {
+    HIPCHK(c, hipMemcpyAsync(p + 2 * gsb, s.mref, db, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(p + 2 * gsb + db, s.hdref, db, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
+}
+
+int mm_state_load(mm_ctx* c, int sample, const void* host, int64_t bytes) {
+  int rc = check_sample(c, sample, true);
+  if (rc != MM_OK) return rc;
+  if (!host) return fail(c, MM_EINVAL, "null buffer");
+  if (c->ls.on) return fail(c, MM_EINVAL, "a line-search run is not checkpointed");
+  Sample& s = c->smp[sample];
+  if (bytes < (int64_t)sizeof(CkptHeader)) return fail(c, MM_EINVAL, "checkpoint too short");
+  CkptHeader hd;
+  std::memcpy(&hd, host, sizeof(hd));
+  if (std::memcmp(hd.magic, kCkptMagic, sizeof(kCkptMagic)) != 0 || hd.version != 1)
+    return fail(c, MM_EINVAL, "not a checkpoint of this library");
+  if (hd.prec != c->prec || hd.nx != s.nx || hd.ny != s.ny || hd.nz != s.nz ||
+      hd.gs != (int32_t)gs_bytes(c) || hd.has_ref != (use_ref(c, s) ? 1 : 0))
+    return fail(c, MM_EINVAL, "checkpoint of another precision, grid or correction setting");
+  const int64_t need = ckpt_bytes(c, s);
+  if (hd.bytes != need || bytes < need) return fail(c, MM_EINVAL, "checkpoint size mismatch");
+  if (!std::isfinite(hd.run.H[0]) || !std::isfinite(hd.run.H[1]) || !std::isfinite(hd.run.H[2]))
+    return fail(c, MM_EINVAL, "checkpoint field not finite");
+  rc = read_state(c, s);   // the device state's pointers and slots are kept
+  if (rc != MM_OK) return rc;
+  MinState& h = *s.st_host;
+  const CkptRun& r = hd.run;
+  h.tau = r.tau;
+  h.torque = r.torque;
+  h.energy = r.energy;
+  for (int q = 0; q < 4; ++q) h.eterm[q] = r.eterm[q];
+  h.ss = r.ss;
+  h.sy = r.sy;
+  h.yy = r.yy;
+  h.best_torque = r.best_torque;
+  h.tol = r.tol;
+  h.tau0 = r.tau0;
+  h.k = r.k;
+  h.best_k = r.best_k;
+  h.evals = r.evals;
+  h.max_iter = r.max_iter;
+  h.stall_iters = r.stall_iters;
+  h.done = r.done;
+  h.mode = r.mode;
+  h.last_tau = r.last_tau;
+  h.last_k = r.last_k;
+  h.pending = r.pending;
+  for (int q = 0; q < 3; ++q) h.H[q] = r.H[q];
+  h.bb_switch = r.bb_switch;
+  h.sweep = 0;
+  h.ls_trial = h.ls_retry = h.ls_nb = 0;
+  h.ls_C = h.ls_Q = h.ls_G = 0.0;
+  h.fin_err = 0;
+  for (int q = 0; q < 3; ++q) s.H[q] = r.H[q];
+  s.fin_pending = false;
+  s.ref_age = hd.ref_age;
+  const unsigned char* p = static_cast<const unsigned char*>(host) + sizeof(hd);
+  const size_t gsb = 3ull * s.N * gs_bytes(c), db = 3ull * s.N * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(s.st, s.st_host, sizeof(MinState), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(s.g, p, gsb, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(s.s, p + gsb, gsb, hipMemcpyHostToDevice, c->stream));
+  if (hd.has_ref) {
+    HIPCHK(c, hipMemcpyAsync(s.mref, p + 2 * gsb, db, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s.hdref, p + 2 * gsb + db, db, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MM_OK;
 }
 
 int mm_mean(mm_ctx* c, int sample, const double* m, double* mavg) {

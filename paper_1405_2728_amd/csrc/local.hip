@@ -145,6 +145,52 @@ __global__ void k_sweep_start(MinState* st, const double* fields, int n_fields, 
   if (n_fields <= 0) st->done = 1;
 }
 
+// Continue a run with new stop limits.  A state whose next action is already
+// set (an update pending, an update applied since the last evaluation, or
+// nothing evaluated yet) only takes the limits; a run that ended at its last
+// evaluation takes that evaluation's decision again under the new limits,
+// as the finish would have taken it: stop at T < tol or k >= max_iter, else
+// the step of eq. (12) from the recorded sums (tau0 at k = 0) becomes the
+// pending update.
+__global__ void k_continue_state(MinState* st, double tol, long long max_iter,
+                                 long long stall_iters) {
+  st->tol = tol;
+  st->max_iter = max_iter;
+  st->stall_iters = stall_iters;
+  st->mode = 0;
+  st->sweep = 0;
+  st->ls_trial = 0;
+  st->ls_retry = 0;
+  st->ls_nb = 0;
+  st->fin_err = 0;
+  if (st->done == -1) return;
+  st->done = 0;
+  const long long k = st->k;
+  if (st->pending != 0 || k != st->last_k || st->evals == 0) return;
+  if (st->torque < tol) {
+    st->done = 1;
+    return;
+  }
+  if (k >= max_iter) {
+    st->done = 2;
+    return;
+  }
+  double v[kNPartial] = {};
+  v[0] = st->ss;
+  v[1] = st->sy;
+  v[2] = st->yy;
+  const double tau = k > 0 ? bb_step(k, st->bb_switch, v, st->tau) : st->tau;
+  st->tau = tau;
+  st->last_tau = tau;
+  st->k = k + 1;
+  st->pending = 1;
+}
+
+void launch_continue_state(hipStream_t s, MinState* st, double tol, long long max_iter,
+                           long long stall_iters) {
+  hipLaunchKernelGGL(k_continue_state, dim3(1), dim3(1), 0, s, st, tol, max_iter, stall_iters);
+}
+
 // Switch the mode of a run without touching its BB history (clears done).
 __global__ void k_set_mode(MinState* st, int mode) {
   st->mode = mode;

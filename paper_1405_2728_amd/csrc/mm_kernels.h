@@ -286,6 +286,12 @@ void launch_sweep_start(hipStream_t s, MinState* st, const double* fields, int n
                         double* mavg_out, long long* iters_out, double inv_N);
 void launch_set_mode(hipStream_t s, MinState* st, int mode);
 void launch_clear_pending(hipStream_t s, MinState* st);
+// Continue a run (mode 0 with the given stop limits) from its state: where
+// the run ended at an evaluation without a step, the decision of that
+// evaluation is taken anew with the new limits (stop, or the step of
+// eq. (12) from the recorded BB sums, which becomes the pending update).
+void launch_continue_state(hipStream_t s, MinState* st, double tol, long long max_iter,
+                           long long stall_iters);
 // fused x passes of the thin-film iteration
 int rows_per_block(int M, int ny, bool single);
 // msub (NULL: none) is subtracted from m before the transform; mcopy (NULL:
