@@ -99,5 +99,69 @@ def build(verbose=True, jobs=None):
     return lib_path()
 
 
+# Host-side sanitizer build (device code as in the library): every source
+# and the driver of tests/host_sanitize/, host code instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer, linked into one program.
+SAN_FLAGS = [
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+    "-gline-tables-only",
+]
+
+
+def sanitize_driver_dir():
+    return os.path.join(os.path.dirname(HERE), "tests", "host_sanitize")
+
+
+def sanitize_exe():
+    return os.path.join(sanitize_driver_dir(), "mm_sanitize")
+
+
+def sanitize_hash():
+    """Hash of the library sources plus the driver source and flags."""
+    h = hashlib.sha256(sources_hash().encode())
+    with open(os.path.join(sanitize_driver_dir(), "driver.cpp"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(SAN_FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
+def sanitize_is_current():
+    exe = sanitize_exe()
+    if not os.path.exists(exe) or not os.path.exists(exe + ".srchash"):
+        return False
+    with open(exe + ".srchash") as fh:
+        return fh.read().strip() == sanitize_hash()
+
+
+def build_sanitized(verbose=True, jobs=None):
+    """Compile the library sources and the driver with host sanitizers into
+    tests/host_sanitize/mm_sanitize (always rebuilds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    hipcc = os.environ.get("HIPCC", "hipcc")
+    objdir = os.path.join(HERE, "_build", "san")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"] + SAN_FLAGS
+    inc = "-I" + os.path.join(os.path.dirname(HERE), "include")
+    cmds, objs = [], []
+    srcs = [os.path.join(HERE, "csrc", f) for f in SOURCES]
+    srcs.append(os.path.join(sanitize_driver_dir(), "driver.cpp"))
+    for src in srcs:
+        obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        cmds.append([hipcc] + compile_flags + [inc, "-c", "-o", obj, src])
+        objs.append(obj)
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    exe = sanitize_exe()
+    _run([hipcc, "--offload-arch=gfx950"] + SAN_FLAGS + ["-o", exe + ".tmp"] + objs, verbose)
+    digest = sanitize_hash()
+    os.replace(exe + ".tmp", exe)
+    with open(exe + ".srchash", "w") as fh:
+        fh.write(digest + "\n")
+    return exe
+
+
 if __name__ == "__main__":
     build()
