@@ -2029,8 +2029,15 @@ int mm_state_load(mm_ctx* c, int sample, const void* host, int64_t bytes) {
     return fail(c, MM_EINVAL, "checkpoint of another precision, grid or correction setting");
   const int64_t need = ckpt_bytes(c, s);
   if (hd.bytes != need || bytes < need) return fail(c, MM_EINVAL, "checkpoint size mismatch");
-  if (!std::isfinite(hd.run.H[0]) || !std::isfinite(hd.run.H[1]) || !std::isfinite(hd.run.H[2]))
-    return fail(c, MM_EINVAL, "checkpoint field not finite");
+  {
+    const CkptRun& r = hd.run;
+    const bool ok = std::isfinite(r.H[0]) && std::isfinite(r.H[1]) && std::isfinite(r.H[2]) &&
+                    std::isfinite(r.tau) && std::isfinite(r.last_tau) && r.k >= 0 &&
+                    r.last_k >= 0 && r.evals >= 0 && r.mode >= 0 && r.mode <= 2 &&
+                    r.pending >= 0 && r.pending <= 1 && r.done >= -1 && r.done <= 3 &&
+                    hd.ref_age >= 0;
+    if (!ok) return fail(c, MM_EINVAL, "checkpoint holds an invalid run state");
+  }
   rc = read_state(c, s);   // the device state's pointers and slots are kept
   if (rc != MM_OK) return rc;
   MinState& h = *s.st_host;
