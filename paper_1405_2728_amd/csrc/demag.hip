@@ -417,7 +417,13 @@ __device__ __forceinline__ void yz_wave_body(cx<T>* __restrict__ A, int ny, int 
   }
   __builtin_amdgcn_wave_barrier();
   cx<T> xo[VL];
-  wfft_inverse<T, VL, false>(u, xo, slice, twy + zoff, lane);
+  // the lane index read again for the inverse: otherwise the compiler keeps
+  // the forward transform's twiddle offsets (lane multiples) across the
+  // product and spills them to scratch memory (single precision at six
+  // waves per SIMD, the persistent double-precision kernels for 3 and 4
+  // layers), with scratch reloads in the inverse transform's chain
+  const int lane_i = thread_index() & 63;
+  wfft_inverse<T, VL, false>(u, xo, slice, twy + zoff, lane_i);
   const bool real_col = kx == 0 || kx == M;
 #pragma unroll
   for (int r = 0; r < VL; ++r) {
