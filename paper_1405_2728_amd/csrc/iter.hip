@@ -469,8 +469,13 @@ __device__ __forceinline__ void xf_w_body(double* __restrict__ m, const T* __res
   cx<T>* reg = sm + (size_t)w * RG;
   if (r < rows) {
     cx<T> v[VL], u[8];
+    // element by element: as one aggregate copy the single element of the
+    // 64-point transform stayed in scratch memory across the barrier
 #pragma unroll
-    for (int q = 0; q < VL; ++q) v[q] = reg[lane + 64 * q];
+    for (int q = 0; q < VL; ++q) {
+      const cx<T>& e = reg[lane + 64 * q];
+      v[q] = mk(e.x, e.y);
+    }
     __builtin_amdgcn_wave_barrier();
     wfft_forward<T, VL, false, 2>(v, u, reg, twx, lane);   // table of length Px = 2M
     __builtin_amdgcn_wave_barrier();

@@ -128,8 +128,13 @@ __device__ __forceinline__ void wfft_inverse(cx<T> (&u)[8], cx<T> (&v)[VL], cx<T
       for (int b = 0; b < 8; ++b) lds[wf_f1(k1 - p * KP, a + 8 * b)] = u[b];
     }
     __builtin_amdgcn_wave_barrier();
+    // element by element: as one aggregate copy the single element of the
+    // 64-point transform stayed in scratch memory across the barrier
 #pragma unroll
-    for (int kk = 0; kk < KP; ++kk) v[p * KP + kk] = lds[wf_f1(kk, lane)];
+    for (int kk = 0; kk < KP; ++kk) {
+      const cx<T>& e = lds[wf_f1(kk, lane)];
+      v[p * KP + kk] = mk(e.x, e.y);
+    }
     __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
